@@ -1,0 +1,159 @@
+"""Pins for the min-entropy oracle (CPU only).
+
+Pinned against: the closed form of a discretised Gaussian's min-entropy
+(with the library normal CDF of scipy as an independent Phi), the paper's
+printed worked example (loose: two-decimal rounding, unstated binning),
+large-sample convergence, and invariants of the correction term.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+import oracle
+import qrng_inputs as qi
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_gaussian_model_against_library_cdf():
+    for mu, sigma in [(128.0, 20.0), (100.3, 8.0), (3.0, 2.0), (250.0, 30.0)]:
+        P = oracle.gaussian_model(8, mu, sigma)
+        assert abs(P.sum() - 1.0) < 1e-12
+        edges = np.arange(-0.5, 256.5, 1.0)
+        cdf = norm.cdf((edges - mu) / sigma)
+        cdf[0], cdf[-1] = 0.0, 1.0
+        assert np.max(np.abs(np.diff(cdf) - P)) < 1e-13
+
+
+def test_closed_form_zero_distance():
+    g = json.load(open(os.path.join(GOLD, "gaussian_closed_form.json")))
+    for case in g["cases"]:
+        P = oracle.gaussian_model(g["N"], g["mu"], case["sigma"])
+        r = oracle.minentropy_dists(P, P, g["N"])
+        closed = -math.log2(math.erf(1.0 / (2.0 * math.sqrt(2.0) * case["sigma"])))
+        assert abs(r["h_min"] - closed) < 1e-12
+        assert abs(r["h_min"] - case["h_min"]) < g["tolerance"]
+        assert r["d_u"] == 0.0 and r["delta_h_m"] == 0.0
+        assert r["h_mod"] == r["h_min"]
+        assert r["argmax_model"] == g["mu"]
+
+
+def attacked_cdf(v, alpha_e, beta_e, i_max):
+    """CDF of V' = alpha_e (1 - I/(beta_e I_max)) I with I ~ N(0,1) (Sec. II.B).
+
+    V' is a downward parabola in I; {V' <= v} is {I <= lower root} union
+    {I >= upper root} (or everything above the vertex)."""
+    a = alpha_e / (beta_e * i_max)          # V' = alpha_e I - a I^2
+    v = np.asarray(v, dtype=np.float64)
+    disc = alpha_e ** 2 - 4.0 * a * v
+    out = np.ones_like(v)
+    ok = disc > 0
+    lo = (alpha_e - np.sqrt(disc[ok])) / (2.0 * a)
+    hi = (alpha_e + np.sqrt(disc[ok])) / (2.0 * a)
+    out[ok] = norm.cdf(lo) + norm.sf(hi)
+    return out
+
+
+def test_worked_example_attack():
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    p = g["params"]
+    N = p["N"]
+    K = 1 << N
+    edges = p["lo"] + np.arange(K + 1) * (p["hi"] - p["lo"]) / K
+    cV = norm.cdf(edges)
+    cA = attacked_cdf(edges, p["alpha_e"], p["beta_e"], p["I_max"])
+    cV[0] = cA[0] = 0.0
+    cV[-1] = cA[-1] = 1.0
+    P, Pa = np.diff(cV), np.diff(cA)
+    # sanity of the attack model: same variance to within the paper's claim
+    r = oracle.minentropy_dists(P, Pa, N)
+    b = g["bands"]
+    assert b["H_V"][0] <= r["h_min"] <= b["H_V"][1]
+    assert b["H_Vp"][0] <= r["h_actual"] <= b["H_Vp"][1]
+    assert b["delta_H_m"][0] <= r["delta_h_m"] <= b["delta_H_m"][1]
+    # the corrected entropy is below the attacked one: no leak (Sec. II.C)
+    assert r["h_mod"] < r["h_actual"]
+    assert r["mutual_info"] > 0
+    leak = 100.0 * r["mutual_info"] / r["h_min"]
+    assert b["leak_percent"][0] <= leak <= b["leak_percent"][1]
+
+
+def test_large_sample_convergence():
+    s = qi.gen_adc(1 << 24, 20.0, seed=5)
+    r = oracle.minentropy_counts(oracle.histogram(s, 8), 8)
+    assert 5.60 <= r["h_mod"] <= 5.648
+    assert abs(r["sigma_hat"] - 20.0) < 0.05
+    assert abs(r["h_min"] - 5.6478) < 0.01
+
+
+def test_given_model_uses_caller_parameters():
+    s = qi.gen_adc(1 << 16, 20.0, seed=6)
+    c = oracle.histogram(s, 8)
+    r = oracle.minentropy_counts(c, 8, mu=128.0, sigma=20.0)
+    assert r["mu_hat"] == 128.0 and r["sigma_hat"] == 20.0
+    P = oracle.gaussian_model(8, 128.0, 20.0)
+    assert abs(r["h_min"] + math.log2(P.max())) < 1e-15
+    d = 0.5 * abs(c[128] / c.sum() - P[128])
+    assert abs(r["d_u"] - d) < 1e-15
+
+
+def test_invariants_random_histograms():
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        K = 256
+        c = rng.integers(0, 1000, K).astype(np.float64)
+        c[int(rng.integers(K))] += 5000
+        Pa = c / c.sum()
+        mu, sigma = rng.uniform(20, 230), rng.uniform(3, 40)
+        P = oracle.gaussian_model(8, mu, sigma)
+        rm = oracle.minentropy_dists(P, Pa, 8, oracle.U_MODEL_ARGMAX)
+        rb = oracle.minentropy_dists(P, Pa, 8, oracle.U_BOTH_ARGMAX)
+        ra = oracle.minentropy_dists(P, Pa, 8, oracle.U_ALL)
+        for r in (rm, rb, ra):
+            assert r["delta_h_m"] >= 0 and r["h_mod"] <= r["h_min"]
+        # larger U can only grow the distance
+        assert rm["d_u"] <= rb["d_u"] <= ra["d_u"] + 1e-15
+        assert ra["d_u"] <= 1.0 + 1e-12
+        # U = both argmaxes bounds the actual min-entropy from below
+        assert rb["h_mod"] <= -math.log2(Pa.max()) + 1e-12
+
+
+def test_delta_monotone_in_distance():
+    P = oracle.gaussian_model(8, 128.0, 20.0)
+    prev = -1.0
+    for eps in np.linspace(0, 0.01, 11):
+        Pa = P.copy()
+        Pa[128] += eps
+        Pa[0] -= eps
+        r = oracle.minentropy_dists(P, Pa, 8)
+        assert r["delta_h_m"] > prev or eps == 0
+        assert abs(r["d_u"] - eps / 2) < 1e-15
+        assert abs(r["delta_h_m"] - math.log2(eps / 2 * 512 + 1)) < 1e-12
+        prev = r["delta_h_m"]
+
+
+@pytest.mark.parametrize("n,N,h,eps,want", [
+    (131072, 8, 5.57, 0.0, 81920),        # single-block workload: 5 bits/sample
+    (1 << 23, 8, 5.64, 0.0, 5242880),
+    (1000, 8, 5.99, 0.0, 625),
+    (1000, 8, 5.0, 10.0, 605),             # eps = 2^-10 costs 20 bits
+    (64, 8, 0.7, 0.0, 0),                  # less than one bit per sample
+    (64, 8, -3.0, 0.0, 0),
+    (64, 8, 8.0, 0.0, 64),
+    (10, 8, 7.5, 50.0, 0),                 # clamped at 0
+])
+def test_output_bits_rule(n, N, h, eps, want):
+    assert oracle.output_bits(n, N, h, eps) == want
+
+
+def test_single_block_workload_gives_81920():
+    c = qi.config(0)
+    s = qi.gen_adc(c["S"], c["sigma"], seed=c["adc_seed"])
+    r = oracle.minentropy_counts(oracle.histogram(s, 8), 8)
+    assert math.floor(r["h_mod"]) == 5
+    assert abs(r["h_mod"] - round(r["h_mod"])) > 1e-9
+    assert oracle.output_bits(c["n"], 8, r["h_mod"]) == c["m_expected"] == 81920
