@@ -1,0 +1,167 @@
+/*
+ * qrng.h -- C ABI of libqrng: QRNG post-processing on one AMD Instinct MI355X
+ * (gfx950): min-entropy estimation with a statistical-distance correction and
+ * Toeplitz-hashing randomness extraction over GF(2).
+ *
+ * Paper: Z. Zhao, "Performance Optimization on Practical Quantum Random
+ * Number Generators: Modification on Min-entropy Evaluation and Acceleration
+ * on Post Processing", arXiv 2011.04130.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Bit strings are packed LSB first into little-endian 64-bit words: bit b is
+ * bit (b % 64) of word b / 64.  Raw ADC samples of N <= 8 bits are one byte
+ * each; the byte buffer viewed as 64-bit words is the packed raw block (bit
+ * 8t + i is bit i of sample t).  Bits past the stated length of an input are
+ * ignored; output bits past m in the last word are written as 0.
+ *
+ * Device pointers ("_dev") refer to memory on the context's device and must be
+ * 8-byte aligned.  The caller owns every buffer it passes; the library never
+ * frees caller memory.  `stream` is a hipStream_t (NULL = the null stream).
+ * Hash calls only enqueue work and return; results are ready when the stream
+ * reaches that point.  Calls that return host values synchronise the stream.
+ *
+ * Errors: argument errors are detected before anything is enqueued and return
+ * QRNG_EINVAL; HIP failures return QRNG_EDEVICE.  The library never aborts.
+ * qrng_last_error() gives a thread-local message for the last failure.
+ * A context may be used from one host thread at a time.
+ */
+#ifndef QRNG_H
+#define QRNG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QRNG_OK = 0,
+  QRNG_EINVAL = -1,       /* bad argument (nothing was enqueued) */
+  QRNG_ENOMEM = -2,       /* device or host allocation failed */
+  QRNG_EDEVICE = -3,      /* a HIP call failed */
+  QRNG_EUNSUPPORTED = -4, /* valid request this path cannot serve */
+  QRNG_EBUSY = -5         /* resource limit (admission) reached */
+} qrng_status;
+
+/* Which extraction kernel to run.  All paths return identical bits. */
+typedef enum {
+  QRNG_PATH_AUTO = 0,   /* library picks (autotuned plan table if loaded) */
+  QRNG_PATH_DIRECT = 1, /* bit-packed AND/parity mat-vec, O(mn) */
+  QRNG_PATH_NTT = 2,    /* exact convolution mod 998244353, O(L log L) */
+  QRNG_PATH_MFMA = 3    /* int8 matrix-core product, shared-seed batches */
+} qrng_path;
+
+/* The set U over which the statistical distance is taken (Sec. II.C). */
+typedef enum {
+  QRNG_U_MODEL_ARGMAX = 0, /* U = {argmax P}, the paper's chain of bounds */
+  QRNG_U_BOTH_ARGMAX = 1,  /* U = {argmax P, argmax P'} (never over-estimates) */
+  QRNG_U_ALL = 2           /* U = all values: total-variation distance */
+} qrng_u_mode;
+
+/* Where the ideal (model) distribution's Gaussian parameters come from. */
+typedef enum {
+  QRNG_MODEL_FIT = 0,  /* mean and population s.d. of the same samples */
+  QRNG_MODEL_GIVEN = 1 /* the caller's mu, sigma (sigma > 0) */
+} qrng_model;
+
+typedef struct qrng_ctx qrng_ctx;
+
+typedef struct {
+  int32_t sample_bits; /* N, 1..8: ADC bits per sample */
+  int32_t model;       /* qrng_model */
+  double mu, sigma;    /* used when model == QRNG_MODEL_GIVEN */
+  int32_t u_mode;      /* qrng_u_mode */
+  int32_t reserved;    /* must be 0 */
+} qrng_me_opts;
+
+typedef struct {
+  double mu_hat, sigma_hat; /* model parameters used */
+  double h_min;             /* -log2 max_x P(x), ideal model (Sec. II.A) */
+  double h_actual;          /* -log2 max_x P'(x), observed histogram */
+  double d_u;               /* (1/2) sum_{x in U} |P'(x) - P(x)| */
+  double delta_h_m;         /* log2(d_U / 2^-(N+1) + 1) */
+  double h_mod;             /* h_min - delta_h_m (Sec. II.C) */
+  uint32_t argmax_model, argmax_empirical;
+  uint64_t samples;
+} qrng_me_result;
+
+/* One block of a batched hash: raw bits x_pool[x_word_off*64 ...] (n bits)
+ * hashed with the first n+m-1 bits of registered seed `seed_id` into
+ * y_pool[y_word_off*64 ...] (m bits).  Blocks must not overlap in y. */
+typedef struct {
+  uint64_t x_word_off;
+  uint64_t n;
+  uint64_t m;
+  uint64_t y_word_off;
+  uint32_t seed_id;
+  uint32_t flags; /* must be 0 */
+} qrng_block;
+
+/* Library version string (static storage). */
+const char *qrng_version(void);
+
+/* Thread-local text of the last error reported by this thread. */
+const char *qrng_last_error(void);
+
+/* Create a context on HIP device `device`: uploads the transform tables.
+ * *ctx receives the handle; destroy it with qrng_destroy. */
+qrng_status qrng_create(qrng_ctx **ctx, int device);
+
+/* Wait for the context's outstanding work and release everything it owns
+ * (workspace, cached seed spectra).  NULL is a no-op. */
+void qrng_destroy(qrng_ctx *ctx);
+
+/* Sec. II: histogram of S samples (uint8, values < 2^N) on the device, then
+ * on the host: the Gaussian model P (fitted or given; codes 0 and 2^N-1 take
+ * the clipped tails), H_min = -log2 max P, the observed P' = counts/S, the
+ * statistical distance d_U over U, Delta H_m = log2(d_U / 2^-(N+1) + 1) and
+ * H_modify = H_min - Delta H_m.  `counts_host` (nullable) receives the 2^N
+ * counts.  Synchronises `stream`.  EINVAL if S == 0, N outside 1..8, a
+ * sample is >= 2^N (detected after the histogram), or a given sigma <= 0. */
+qrng_status qrng_minentropy(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
+                            const qrng_me_opts *opts, qrng_me_result *out_host,
+                            uint64_t *counts_host, void *stream);
+
+/* Sec. III.B output length m = n H/N - 2 log2(1/eps), with H counted in whole
+ * bits per sample (floor of h_mod, at least 0), the security term rounded up
+ * (log2_inv_eps >= 0), and m clamped to [0, n].  Pure host function. */
+qrng_status qrng_output_bits(uint64_t n, int sample_bits, double h_mod,
+                             double log2_inv_eps, uint64_t *m_out);
+
+/* Sec. III.B Toeplitz hash y = T x mod 2 of one block: x is n raw bits, the
+ * seed is n+m-1 bits, T[i][j] = seed[n-1+i-j] (first row seed bits n-1 down to
+ * 0, first column seed bits n-1 up to n+m-2), y is m bits.  y_dev holds
+ * ceil(m/64) words and must not overlap x or the seed.  0 < n; m <= n; m == 0
+ * is a no-op.  The NTT path needs n < 998244353.  Enqueued on `stream`. */
+qrng_status qrng_toeplitz_hash(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
+                               const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
+                               int path, void *stream);
+
+/* Register a seed of L bits for reuse.  The memory must stay unchanged and
+ * allocated until qrng_seed_unregister or qrng_destroy; transform-domain
+ * copies of it are computed on first use per block shape and cached. */
+qrng_status qrng_seed_register(qrng_ctx *ctx, const uint64_t *seed_dev, uint64_t L,
+                               uint32_t *seed_id);
+qrng_status qrng_seed_unregister(qrng_ctx *ctx, uint32_t seed_id);
+
+/* As qrng_toeplitz_hash with a registered seed (its first n+m-1 bits). */
+qrng_status qrng_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
+                                      uint32_t seed_id, uint64_t m, uint64_t *y_dev,
+                                      int path, void *stream);
+
+/* Hash many blocks (Sec. III.E: a long raw sequence split into blocks) in one
+ * enqueued batch.  `blocks_host` lists nblocks descriptors (host memory);
+ * x_pool_dev / y_pool_dev are the raw and output pools the offsets refer to.
+ * Each block's result equals qrng_toeplitz_hash_seeded on that block alone.
+ * Blocks are grouped by shape class and path; `path` forces one path for all
+ * (AUTO lets the plan choose per class). */
+qrng_status qrng_toeplitz_hash_batched(qrng_ctx *ctx, const qrng_block *blocks_host,
+                                       uint32_t nblocks, const uint64_t *x_pool_dev,
+                                       uint64_t *y_pool_dev, int path, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRNG_H */

@@ -265,6 +265,11 @@ def gaussian_model(N: int, mu: float, sigma: float) -> np.ndarray:
     """
     K = 1 << N
     P = np.empty(K, dtype=np.float64)
+    if not sigma > 0:
+        # every sample equal: the fitted model is a point mass
+        P[:] = 0.0
+        P[int(min(max(math.floor(mu + 0.5), 0), K - 1))] = 1.0
+        return P
     for v in range(K):
         lo = 0.0 if v == 0 else _phi((v - 0.5 - mu) / sigma)
         hi = 1.0 if v == K - 1 else _phi((v + 0.5 - mu) / sigma)
@@ -347,9 +352,13 @@ def output_bits(n: int, N: int, h_mod: float, log2_inv_eps: float = 0.0) -> int:
     """Output length m = n H/N - 2 log2(1/eps) (Sec. III.B, leftover hash lemma).
 
     Reading: H is counted in whole bits per sample (floor of H_modify, never
-    below 0), the security term is rounded up, and m is clamped to [0, n].
+    below 0 and never above the sample width N), the security term is rounded
+    up, and m is clamped at 0 (it cannot exceed n once H <= N).
     """
-    h = max(0, math.floor(h_mod)) if math.isfinite(h_mod) else 0
+    if math.isnan(h_mod):
+        raise ValueError("h_mod is NaN")
+    h = math.floor(h_mod) if math.isfinite(h_mod) else (N if h_mod > 0 else 0)
+    h = min(max(h, 0), N)
     sec = math.ceil(2.0 * log2_inv_eps) if log2_inv_eps > 0 else 0
     m = (n * h) // N - sec
     return int(min(max(m, 0), n))

@@ -1,0 +1,110 @@
+"""ctypes declarations of the C ABI in include/qrng.h (no torch needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libqrng.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = 0, -1, -2, -3, -4, -5
+PATH_AUTO, PATH_DIRECT, PATH_NTT, PATH_MFMA = 0, 1, 2, 3
+U_MODEL_ARGMAX, U_BOTH_ARGMAX, U_ALL = 0, 1, 2
+MODEL_FIT, MODEL_GIVEN = 0, 1
+
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+          EUNSUPPORTED: "EUNSUPPORTED", EBUSY: "EBUSY"}
+
+
+class QrngError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class MeOpts(ctypes.Structure):
+    _fields_ = [("sample_bits", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("u_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MeResult(ctypes.Structure):
+    _fields_ = [("mu_hat", ctypes.c_double), ("sigma_hat", ctypes.c_double),
+                ("h_min", ctypes.c_double), ("h_actual", ctypes.c_double),
+                ("d_u", ctypes.c_double), ("delta_h_m", ctypes.c_double),
+                ("h_mod", ctypes.c_double), ("argmax_model", ctypes.c_uint32),
+                ("argmax_empirical", ctypes.c_uint32), ("samples", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Block(ctypes.Structure):
+    _fields_ = [("x_word_off", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("m", ctypes.c_uint64), ("y_word_off", ctypes.c_uint64),
+                ("seed_id", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+# every symbol the header declares
+EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
+           "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
+           "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
+           "qrng_toeplitz_hash_batched"]
+
+
+def load_library(path: str | None = None):
+    """Load libqrng.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError("libqrng.so is not built (%s); run python -m paper_2011_04130_amd.build" % p)
+    lib = ctypes.CDLL(p)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    lib.qrng_version.restype = ctypes.c_char_p
+    lib.qrng_last_error.restype = ctypes.c_char_p
+    lib.qrng_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.qrng_create.restype = i32
+    lib.qrng_destroy.argtypes = [vp]
+    lib.qrng_destroy.restype = None
+    lib.qrng_minentropy.argtypes = [vp, vp, u64, ctypes.POINTER(MeOpts),
+                                    ctypes.POINTER(MeResult), ctypes.POINTER(u64), vp]
+    lib.qrng_minentropy.restype = i32
+    lib.qrng_output_bits.argtypes = [u64, i32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(u64)]
+    lib.qrng_output_bits.restype = i32
+    lib.qrng_toeplitz_hash.argtypes = [vp, vp, u64, vp, u64, vp, i32, vp]
+    lib.qrng_toeplitz_hash.restype = i32
+    lib.qrng_seed_register.argtypes = [vp, vp, u64, ctypes.POINTER(u32)]
+    lib.qrng_seed_register.restype = i32
+    lib.qrng_seed_unregister.argtypes = [vp, u32]
+    lib.qrng_seed_unregister.restype = i32
+    lib.qrng_toeplitz_hash_seeded.argtypes = [vp, vp, u64, u32, u64, vp, i32, vp]
+    lib.qrng_toeplitz_hash_seeded.restype = i32
+    lib.qrng_toeplitz_hash_batched.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp,
+                                               i32, vp]
+    lib.qrng_toeplitz_hash_batched.restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = load_library().qrng_last_error().decode(errors="replace")
+        raise QrngError(status, msg)
+
+
+def version() -> str:
+    return load_library().qrng_version().decode()
+
+
+def output_bits(n: int, sample_bits: int, h_mod: float, log2_inv_eps: float = 0.0) -> int:
+    """m = n H/N - 2 log2(1/eps) with H in whole bits per sample (host only)."""
+    out = ctypes.c_uint64()
+    check(load_library().qrng_output_bits(n, sample_bits, h_mod, log2_inv_eps,
+                                          ctypes.byref(out)))
+    return int(out.value)

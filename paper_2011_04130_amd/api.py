@@ -1,0 +1,158 @@
+"""Torch-facing wrapper of the C ABI: device buffers are torch tensors.
+
+Bit strings are int64 tensors holding the LSB-first 64-bit words (torch has
+no general uint64 arithmetic; only the bit pattern matters).  Samples are
+uint8 tensors.  Every call runs on the tensors' device, on torch's current
+stream for that device unless a stream is given.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, U_MODEL_ARGMAX, Block, MeOpts, MeResult,
+                   QrngError, check, load_library)
+
+
+def _words(bits: int) -> int:
+    return (bits + 63) // 64
+
+
+def _stream(torch, device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A libqrng context on one GPU (tables, workspace, seed cache)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libqrng needs a ROCm GPU; none is visible")
+        self._torch = torch
+        self._lib = load_library()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        check(self._lib.qrng_create(ctypes.byref(h), self.device))
+        self._h = h
+        self._seeds = {}
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.qrng_destroy(self._h)
+            self._h = None
+            self._seeds.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ----------------------------------------------------------
+    def _dev_tensor(self, t, name, dtype=None):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError("%s must live on cuda:%d" % (name, self.device))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError("%s must have dtype %s" % (name, dtype))
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _out(self, y, m):
+        torch = self._torch
+        if y is None:
+            return torch.empty(max(_words(m), 1), dtype=torch.int64,
+                               device="cuda:%d" % self.device)
+        if y.numel() * y.element_size() < _words(m) * 8:
+            raise ValueError("output buffer too small for %d bits" % m)
+        return y
+
+    # -- Sec. II ------------------------------------------------------------
+    def minentropy(self, samples, sample_bits: int = 8, model: int = MODEL_FIT,
+                   mu: float = 0.0, sigma: float = 0.0, u_mode: int = U_MODEL_ARGMAX,
+                   stream=None, want_counts: bool = False) -> dict:
+        torch = self._torch
+        p = self._dev_tensor(samples, "samples", torch.uint8)
+        opts = MeOpts(sample_bits, model, mu, sigma, u_mode, 0)
+        res = MeResult()
+        counts = (ctypes.c_uint64 * (1 << sample_bits))() if want_counts else None
+        check(self._lib.qrng_minentropy(self._h, p, samples.numel(), ctypes.byref(opts),
+                                        ctypes.byref(res), counts,
+                                        _stream(torch, self.device, stream)))
+        out = res.as_dict()
+        if want_counts:
+            out["counts"] = list(counts)
+        return out
+
+    # -- Sec. III.B ---------------------------------------------------------
+    def hash(self, x, n: int, seed, m: int, y=None, path: int = PATH_AUTO, stream=None):
+        """y = T x mod 2 for one block (returns the int64 word tensor y)."""
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        sp = self._dev_tensor(seed, "seed")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        if m and seed.numel() * seed.element_size() < _words(n + m - 1) * 8:
+            raise ValueError("seed holds fewer than n+m-1 bits")
+        y = self._out(y, m)
+        yp = self._dev_tensor(y, "y")
+        check(self._lib.qrng_toeplitz_hash(self._h, xp, n, sp, m, yp, path,
+                                           _stream(torch, self.device, stream)))
+        return y
+
+    def register_seed(self, seed, L: int) -> int:
+        sp = self._dev_tensor(seed, "seed")
+        if seed.numel() * seed.element_size() < _words(L) * 8:
+            raise ValueError("seed holds fewer than L bits")
+        sid = ctypes.c_uint32()
+        check(self._lib.qrng_seed_register(self._h, sp, L, ctypes.byref(sid)))
+        self._seeds[sid.value] = seed  # keep the memory alive while registered
+        return sid.value
+
+    def unregister_seed(self, seed_id: int) -> None:
+        check(self._lib.qrng_seed_unregister(self._h, seed_id))
+        self._seeds.pop(seed_id, None)
+
+    def hash_seeded(self, x, n: int, seed_id: int, m: int, y=None, path: int = PATH_AUTO,
+                    stream=None):
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        y = self._out(y, m)
+        yp = self._dev_tensor(y, "y")
+        check(self._lib.qrng_toeplitz_hash_seeded(self._h, xp, n, seed_id, m, yp, path,
+                                                  _stream(torch, self.device, stream)))
+        return y
+
+    # -- Sec. III.E ---------------------------------------------------------
+    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
+        """blocks: iterable of (x_word_off, n, m, y_word_off, seed_id)."""
+        torch = self._torch
+        bl = list(blocks)
+        arr = (Block * max(len(bl), 1))()
+        xw = x_pool.numel() * x_pool.element_size() // 8
+        yw = y_pool.numel() * y_pool.element_size() // 8
+        for i, (xo, n, m, yo, sid) in enumerate(bl):
+            if xo + _words(n) > xw or yo + _words(m) > yw:
+                raise ValueError("block %d lies outside its pool" % i)
+            arr[i] = Block(xo, n, m, yo, sid, 0)
+        xp = self._dev_tensor(x_pool, "x_pool")
+        yp = self._dev_tensor(y_pool, "y_pool")
+        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(bl), xp, yp, path,
+                                                   _stream(torch, self.device, stream)))
+        return y_pool
+
+
+__all__ = ["Context", "QrngError"]

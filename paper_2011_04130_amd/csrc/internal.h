@@ -1,0 +1,60 @@
+// Internal interfaces between the C-ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qrng {
+
+// ---------------------------------------------------------------- NTT path
+// Per-sub-length twiddle tables (w, floor(w 2^32/p)) and the two-level
+// Montgomery table of the 2^23-rd root used by the four-step twiddles.
+struct TwTables {
+  const uint2* fwd;
+  const uint2* inv;
+  const uint32_t* g_lo;  // 4096 entries: w^j 2^32 mod p
+  const uint32_t* g_hi;  // 2048 entries: w^(4096 j) 2^32 mod p
+};
+
+// Host-built table contents (sizes in entries).
+int tw_total_entries();
+void build_tw_tables(uint2* fwd, uint2* inv, uint32_t* g_lo, uint32_t* g_hi);
+
+// Shape of the exact convolution for an m x n hash.
+struct NttPlan {
+  int log_nc;       // transform length Nc = 2^log_nc
+  int log1, log2;   // Nc = N1 * N2 (N1 = 1: one fused kernel)
+  int nx, ny;       // raw-block chunks and output chunks
+  int64_t bx, by;   // chunk lengths
+  int nwin;         // seed windows = nx + ny - 1
+};
+bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* plan);
+// workspace (uint32 entries) for seed windows and for one hash of `batch` blocks
+uint64_t ntt_seed_elems(const NttPlan& p);
+uint64_t ntt_work_elems(const NttPlan& p, int batch);
+
+// Transform-domain seed: nwin arrays of Nc words (Montgomery form, 1/Nc folded).
+hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_t n,
+                            uint64_t m, uint32_t* W, uint32_t* work,
+                            const TwTables& tw, hipStream_t s);
+// Hash `batch` equal blocks: block z reads raw bits from x_bits + z*x_stride_bits
+// and writes y_bits + z*y_stride_bits (both strides multiples of 64).
+hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
+                    const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
+                    uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
+                    hipStream_t s);
+
+// ------------------------------------------------------------- direct path
+// `batch` blocks sharing one seed: block z reads x_bits + z*x_stride_bits and
+// writes y_bits + z*y_stride_bits (strides multiples of 64).
+uint64_t direct_work_words(uint64_t n, int batch);
+hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits,
+                       uint64_t m, uint32_t* y_bits, uint32_t* work, int num_cus,
+                       hipStream_t s, int batch, uint64_t x_stride_bits,
+                       uint64_t y_stride_bits);
+
+// ------------------------------------------------------------- histogram
+hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
+                        unsigned long long* counts /* nbins + 1 */, int num_cus,
+                        hipStream_t s);
+
+}  // namespace qrng

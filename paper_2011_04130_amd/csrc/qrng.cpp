@@ -1,0 +1,506 @@
+// C ABI of libqrng (declared in include/qrng.h): argument validation, device
+// context, workspace and seed-spectrum cache, path selection, and the host
+// part of the min-entropy estimate (paper Sec. II).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/qrng.h"
+#include "internal.h"
+
+using namespace qrng;
+
+namespace {
+
+thread_local std::string g_err;
+
+qrng_status fail(qrng_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(QRNG_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+struct Seed {
+  const uint64_t* ptr;
+  uint64_t L;
+  // (n, m) -> transform-domain seed windows for the NTT path
+  std::map<std::pair<uint64_t, uint64_t>, uint32_t*> spectra;
+};
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+uint64_t words64(uint64_t bits) { return (bits + 63) / 64; }
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct qrng_ctx {
+  int device = 0;
+  int num_cus = 256;
+  uint2* tw_fwd = nullptr;
+  uint2* tw_inv = nullptr;
+  uint32_t* g_lo = nullptr;
+  uint32_t* g_hi = nullptr;
+  TwTables tw{};
+  uint32_t* work = nullptr;  // general workspace
+  uint64_t work_words = 0;
+  unsigned long long* counts_dev = nullptr;
+  unsigned long long* counts_host = nullptr;  // pinned
+  std::map<uint32_t, Seed> seeds;
+  uint32_t next_seed = 1;
+};
+
+namespace {
+
+qrng_status ensure_work(qrng_ctx* c, uint64_t words) {
+  if (words <= c->work_words) return QRNG_OK;
+  if (c->work) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(c->work));
+    c->work = nullptr;
+    c->work_words = 0;
+  }
+  uint64_t want = std::max<uint64_t>(words, 1u << 20);
+  if (hipMalloc(&c->work, want * 4) != hipSuccess)
+    return fail(QRNG_ENOMEM, "workspace of %llu bytes", (unsigned long long)(want * 4));
+  c->work_words = want;
+  return QRNG_OK;
+}
+
+qrng_status check_hash_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
+                            uint64_t m, const uint64_t* y, int path) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  if (!x || !seed || !y) return fail(QRNG_EINVAL, "null buffer");
+  if (!aligned8(x) || !aligned8(seed) || !aligned8(y))
+    return fail(QRNG_EINVAL, "buffers must be 8-byte aligned");
+  if (n == 0) return fail(QRNG_EINVAL, "n must be positive");
+  if (m > n) return fail(QRNG_EINVAL, "m (%llu) exceeds n (%llu)", (unsigned long long)m,
+                         (unsigned long long)n);
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  if (m == 0) return QRNG_OK;
+  const uint64_t L = n + m - 1;
+  if (overlap(y, words64(m) * 8, x, words64(n) * 8))
+    return fail(QRNG_EINVAL, "output overlaps the raw block");
+  if (overlap(y, words64(m) * 8, seed, words64(L) * 8))
+    return fail(QRNG_EINVAL, "output overlaps the seed");
+  return QRNG_OK;
+}
+
+// Default path choice until a tuned plan table says otherwise: the direct
+// product costs m n / 32 bit-ops, the transform about 40 (n+m) log2(n+m)
+// modular ops; the crossover on MI355X sits near n = 2^15.
+int choose_path(uint64_t n, uint64_t m) {
+  if (n < (1u << 15)) return QRNG_PATH_DIRECT;
+  NttPlan p;
+  if (!ntt_make_plan(n, m, &p)) return QRNG_PATH_DIRECT;
+  return QRNG_PATH_NTT;
+}
+
+qrng_status run_direct(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
+                       uint64_t m, uint64_t* y, hipStream_t s, int batch, uint64_t xs,
+                       uint64_t ys) {
+  qrng_status st = ensure_work(ctx, direct_work_words(n, batch));
+  if (st) return st;
+  HIP_TRY(direct_hash(reinterpret_cast<const uint32_t*>(x), n,
+                      reinterpret_cast<const uint32_t*>(seed), m, reinterpret_cast<uint32_t*>(y),
+                      ctx->work, ctx->num_cus, s, batch, xs, ys));
+  return QRNG_OK;
+}
+
+// NTT hash; W == nullptr computes the seed windows into the workspace first.
+qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
+                    const uint32_t* W, uint64_t m, uint64_t* y, hipStream_t s, int batch,
+                    uint64_t xs, uint64_t ys) {
+  NttPlan p;
+  if (!ntt_make_plan(n, m, &p))
+    return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
+                (unsigned long long)m);
+  const uint64_t seed_words = W ? 0 : ntt_seed_elems(p);
+  const uint64_t work = std::max<uint64_t>(ntt_work_elems(p, batch), ntt_work_elems(p, 1));
+  qrng_status st = ensure_work(ctx, seed_words + work);
+  if (st) return st;
+  if (!W) {
+    uint32_t* Wt = ctx->work + work;
+    HIP_TRY(ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(seed), n, m, Wt, ctx->work,
+                             ctx->tw, s));
+    W = Wt;
+  }
+  HIP_TRY(ntt_hash(p, reinterpret_cast<const uint32_t*>(x), n, m, W,
+                   reinterpret_cast<uint32_t*>(y), ctx->work, batch, xs, ys, ctx->tw, s));
+  return QRNG_OK;
+}
+
+// Cached seed windows of a registered seed for shape (n, m).
+qrng_status seed_spectra(qrng_ctx* ctx, Seed& sd, uint64_t n, uint64_t m, hipStream_t s,
+                         const uint32_t** out) {
+  auto key = std::make_pair(n, m);
+  auto it = sd.spectra.find(key);
+  if (it != sd.spectra.end()) {
+    *out = it->second;
+    return QRNG_OK;
+  }
+  NttPlan p;
+  if (!ntt_make_plan(n, m, &p))
+    return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
+                (unsigned long long)m);
+  uint32_t* W = nullptr;
+  if (hipMalloc(&W, ntt_seed_elems(p) * 4) != hipSuccess)
+    return fail(QRNG_ENOMEM, "seed spectra");
+  qrng_status st = ensure_work(ctx, ntt_work_elems(p, 1) + 1);
+  if (st) {
+    (void)hipFree(W);
+    return st;
+  }
+  hipError_t e = ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(sd.ptr), n, m, W,
+                                  ctx->work, ctx->tw, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(W);
+    return fail(QRNG_EDEVICE, "seed spectra: %s", hipGetErrorString(e));
+  }
+  sd.spectra[key] = W;
+  *out = W;
+  return QRNG_OK;
+}
+
+qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
+                     Seed* sd, uint64_t m, uint64_t* y, int path, hipStream_t s, int batch,
+                     uint64_t xs, uint64_t ys) {
+  if (path == QRNG_PATH_AUTO) path = choose_path(n, m);
+  if (path == QRNG_PATH_DIRECT) return run_direct(ctx, x, n, seed, m, y, s, batch, xs, ys);
+  if (path == QRNG_PATH_NTT) {
+    const uint32_t* W = nullptr;
+    if (sd) {
+      qrng_status st = seed_spectra(ctx, *sd, n, m, s, &W);
+      if (st) return st;
+    }
+    return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys);
+  }
+  return fail(QRNG_EUNSUPPORTED, "path %d is not available for this call", path);
+}
+
+double phi(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
+
+// Sec. II on the host: model P, H_min, d_U, Delta H_m, H_modify.
+void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o,
+                       qrng_me_result* r) {
+  const int K = 1 << N;
+  double S = 0.0;
+  for (int v = 0; v < K; ++v) S += (double)c[v];
+  double mu, sigma;
+  if (o.model == QRNG_MODEL_GIVEN) {
+    mu = o.mu;
+    sigma = o.sigma;
+  } else {
+    double s1 = 0.0;
+    for (int v = 0; v < K; ++v) s1 += (double)v * (double)c[v];
+    mu = s1 / S;
+    double s2 = 0.0;
+    for (int v = 0; v < K; ++v) s2 += ((double)v - mu) * ((double)v - mu) * (double)c[v];
+    sigma = std::sqrt(s2 / S);
+  }
+  std::vector<double> P(K);
+  if (sigma > 0.0) {
+    for (int v = 0; v < K; ++v) {
+      const double lo = v == 0 ? 0.0 : phi(((double)v - 0.5 - mu) / sigma);
+      const double hi = v == K - 1 ? 1.0 : phi(((double)v + 0.5 - mu) / sigma);
+      P[v] = hi - lo;
+    }
+  } else {  // every sample equal: the model is a point mass
+    const double at = std::min<double>(std::max<double>(std::floor(mu + 0.5), 0.0), K - 1);
+    for (int v = 0; v < K; ++v) P[v] = (v == (int)at) ? 1.0 : 0.0;
+  }
+  int um = 0, ua = 0;
+  for (int v = 1; v < K; ++v) {
+    if (P[v] > P[um]) um = v;
+    if (c[v] > c[ua]) ua = v;
+  }
+  std::vector<int> U;
+  if (o.u_mode == QRNG_U_MODEL_ARGMAX) {
+    U.push_back(um);
+  } else if (o.u_mode == QRNG_U_BOTH_ARGMAX) {
+    U.push_back(std::min(um, ua));
+    if (ua != um) U.push_back(std::max(um, ua));
+  } else {
+    for (int v = 0; v < K; ++v) U.push_back(v);
+  }
+  double d = 0.0;
+  for (int u : U) d += std::fabs((double)c[u] / S - P[u]);
+  d *= 0.5;
+  r->mu_hat = mu;
+  r->sigma_hat = sigma;
+  r->h_min = -std::log2(P[um]);
+  r->h_actual = c[ua] ? -std::log2((double)c[ua] / S) : INFINITY;
+  r->d_u = d;
+  r->delta_h_m = std::log2(d * std::ldexp(1.0, N + 1) + 1.0);
+  r->h_mod = r->h_min - r->delta_h_m;
+  r->argmax_model = (uint32_t)um;
+  r->argmax_empirical = (uint32_t)ua;
+  r->samples = (uint64_t)S;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qrng_version(void) { return "libqrng 0.1 (gfx950)"; }
+
+const char* qrng_last_error(void) { return g_err.c_str(); }
+
+qrng_status qrng_create(qrng_ctx** out, int device) {
+  if (!out) return fail(QRNG_EINVAL, "null output handle");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(QRNG_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(QRNG_EINVAL, "device %d out of range", device);
+  DeviceGuard g(device);
+  qrng_ctx* c = new qrng_ctx();
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
+  const int T = tw_total_entries();
+  std::vector<uint2> f(T), iv(T);
+  std::vector<uint32_t> lo(4096), hi(2048);
+  build_tw_tables(f.data(), iv.data(), lo.data(), hi.data());
+  bool ok = hipMalloc(&c->tw_fwd, T * sizeof(uint2)) == hipSuccess &&
+            hipMalloc(&c->tw_inv, T * sizeof(uint2)) == hipSuccess &&
+            hipMalloc(&c->g_lo, 4096 * 4) == hipSuccess &&
+            hipMalloc(&c->g_hi, 2048 * 4) == hipSuccess &&
+            hipMalloc(&c->counts_dev, 257 * 8) == hipSuccess &&
+            hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMemcpy(c->tw_fwd, f.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(c->tw_inv, iv.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(c->g_lo, lo.data(), 4096 * 4, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(c->g_hi, hi.data(), 2048 * 4, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    qrng_destroy(c);
+    return fail(QRNG_EDEVICE, "context setup on device %d failed", device);
+  }
+  c->tw = TwTables{c->tw_fwd, c->tw_inv, c->g_lo, c->g_hi};
+  *out = c;
+  return QRNG_OK;
+}
+
+void qrng_destroy(qrng_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->seeds)
+    for (auto& sp : kv.second.spectra) (void)hipFree(sp.second);
+  if (c->tw_fwd) (void)hipFree(c->tw_fwd);
+  if (c->tw_inv) (void)hipFree(c->tw_inv);
+  if (c->g_lo) (void)hipFree(c->g_lo);
+  if (c->g_hi) (void)hipFree(c->g_hi);
+  if (c->work) (void)hipFree(c->work);
+  if (c->counts_dev) (void)hipFree(c->counts_dev);
+  if (c->counts_host) (void)hipHostFree(c->counts_host);
+  delete c;
+}
+
+qrng_status qrng_output_bits(uint64_t n, int sample_bits, double h_mod, double log2_inv_eps,
+                             uint64_t* m_out) {
+  if (!m_out) return fail(QRNG_EINVAL, "null output");
+  if (sample_bits < 1 || sample_bits > 16) return fail(QRNG_EINVAL, "sample_bits out of range");
+  if (std::isnan(h_mod) || std::isnan(log2_inv_eps) || log2_inv_eps < 0)
+    return fail(QRNG_EINVAL, "bad entropy or security parameter");
+  // whole bits per sample, never below 0 nor above the sample width
+  double h = std::floor(h_mod);
+  if (!(h > 0)) h = 0;
+  if (h > sample_bits) h = sample_bits;
+  const uint64_t base = (uint64_t)((unsigned __int128)n * (uint64_t)h / (uint64_t)sample_bits);
+  const double secd = std::ceil(2.0 * log2_inv_eps);
+  const uint64_t sec = secd >= 1.8e19 ? UINT64_MAX : (uint64_t)secd;
+  *m_out = base > sec ? base - sec : 0;
+  return QRNG_OK;
+}
+
+qrng_status qrng_minentropy(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
+                            const qrng_me_opts* opts, qrng_me_result* out,
+                            uint64_t* counts_host, void* stream) {
+  if (!ctx || !samples || !opts || !out) return fail(QRNG_EINVAL, "null argument");
+  const int N = opts->sample_bits;
+  if (N < 1 || N > 8) return fail(QRNG_EINVAL, "sample_bits must be 1..8 for byte samples");
+  if (S == 0) return fail(QRNG_EINVAL, "no samples");
+  if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
+    return fail(QRNG_EINVAL, "unknown model");
+  if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
+    return fail(QRNG_EINVAL, "unknown U mode");
+  if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
+  if (opts->model == QRNG_MODEL_GIVEN &&
+      !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
+    return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int K = 1 << N;
+  HIP_TRY(histogram_u8(samples, S, K, ctx->counts_dev, ctx->num_cus, s));
+  HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ctx->counts_host[K])
+    return fail(QRNG_EINVAL, "%llu samples are >= 2^%d", ctx->counts_host[K], N);
+  if (counts_host)
+    for (int v = 0; v < K; ++v) counts_host[v] = ctx->counts_host[v];
+  minentropy_finish(ctx->counts_host, N, *opts, out);
+  return QRNG_OK;
+}
+
+qrng_status qrng_toeplitz_hash(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                               const uint64_t* seed, uint64_t m, uint64_t* y, int path,
+                               void* stream) {
+  qrng_status st = check_hash_args(ctx, x, n, seed, m, y, path);
+  if (st || m == 0) return st;
+  DeviceGuard g(ctx->device);
+  return hash_one(ctx, x, n, seed, nullptr, m, y, path, reinterpret_cast<hipStream_t>(stream),
+                  1, 0, 0);
+}
+
+qrng_status qrng_seed_register(qrng_ctx* ctx, const uint64_t* seed, uint64_t L,
+                               uint32_t* seed_id) {
+  if (!ctx || !seed || !seed_id) return fail(QRNG_EINVAL, "null argument");
+  if (!aligned8(seed)) return fail(QRNG_EINVAL, "seed must be 8-byte aligned");
+  if (L == 0) return fail(QRNG_EINVAL, "empty seed");
+  const uint32_t id = ctx->next_seed++;
+  ctx->seeds[id] = Seed{seed, L, {}};
+  *seed_id = id;
+  return QRNG_OK;
+}
+
+qrng_status qrng_seed_unregister(qrng_ctx* ctx, uint32_t seed_id) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  auto it = ctx->seeds.find(seed_id);
+  if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  DeviceGuard g(ctx->device);
+  if (!it->second.spectra.empty()) HIP_TRY(hipDeviceSynchronize());
+  for (auto& sp : it->second.spectra) (void)hipFree(sp.second);
+  ctx->seeds.erase(it);
+  return QRNG_OK;
+}
+
+qrng_status qrng_toeplitz_hash_seeded(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                      uint32_t seed_id, uint64_t m, uint64_t* y, int path,
+                                      void* stream) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  auto it = ctx->seeds.find(seed_id);
+  if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  Seed& sd = it->second;
+  qrng_status st = check_hash_args(ctx, x, n, sd.ptr, m, y, path);
+  if (st || m == 0) return st;
+  if (n + m - 1 > sd.L)
+    return fail(QRNG_EINVAL, "seed has %llu bits, block needs %llu", (unsigned long long)sd.L,
+                (unsigned long long)(n + m - 1));
+  DeviceGuard g(ctx->device);
+  return hash_one(ctx, x, n, sd.ptr, &sd, m, y, path, reinterpret_cast<hipStream_t>(stream), 1,
+                  0, 0);
+}
+
+qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
+                                       uint32_t nblocks, const uint64_t* x_pool,
+                                       uint64_t* y_pool, int path, void* stream) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  if (nblocks == 0) return QRNG_OK;
+  if (!blocks || !x_pool || !y_pool) return fail(QRNG_EINVAL, "null argument");
+  if (!aligned8(x_pool) || !aligned8(y_pool)) return fail(QRNG_EINVAL, "pools must be aligned");
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  // validate every descriptor before enqueueing anything
+  std::vector<std::pair<uint64_t, uint64_t>> yr;
+  yr.reserve(nblocks);
+  for (uint32_t i = 0; i < nblocks; ++i) {
+    const qrng_block& b = blocks[i];
+    if (b.flags) return fail(QRNG_EINVAL, "block %u: flags must be 0", i);
+    if (b.n == 0 || b.m > b.n) return fail(QRNG_EINVAL, "block %u: need 0 < n and m <= n", i);
+    auto it = ctx->seeds.find(b.seed_id);
+    if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "block %u: unknown seed %u", i, b.seed_id);
+    if (b.m && b.n + b.m - 1 > it->second.L)
+      return fail(QRNG_EINVAL, "block %u: seed too short", i);
+    if (b.m) yr.emplace_back(b.y_word_off, b.y_word_off + words64(b.m));
+  }
+  std::sort(yr.begin(), yr.end());
+  for (size_t i = 1; i < yr.size(); ++i)
+    if (yr[i].first < yr[i - 1].second) return fail(QRNG_EINVAL, "output ranges overlap");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // group equal shapes whose offsets advance by constant strides: one launch each
+  std::map<std::tuple<uint64_t, uint64_t, uint32_t>, std::vector<uint32_t>> groups;
+  for (uint32_t i = 0; i < nblocks; ++i)
+    if (blocks[i].m) groups[{blocks[i].n, blocks[i].m, blocks[i].seed_id}].push_back(i);
+  for (auto& kv : groups) {
+    const uint64_t n = std::get<0>(kv.first), m = std::get<1>(kv.first);
+    Seed& sd = ctx->seeds[std::get<2>(kv.first)];
+    const std::vector<uint32_t>& ids = kv.second;
+    int p = path == QRNG_PATH_AUTO ? choose_path(n, m) : path;
+    size_t i = 0;
+    while (i < ids.size()) {
+      // longest run with constant x and y strides
+      size_t j = i + 1;
+      int64_t dx = 0, dy = 0;
+      if (j < ids.size()) {
+        dx = (int64_t)blocks[ids[j]].x_word_off - (int64_t)blocks[ids[i]].x_word_off;
+        dy = (int64_t)blocks[ids[j]].y_word_off - (int64_t)blocks[ids[i]].y_word_off;
+        if (dx < 0 || dy < 0) dx = dy = -1;
+        while (dx >= 0 && j < ids.size() &&
+               (int64_t)blocks[ids[j]].x_word_off - (int64_t)blocks[ids[j - 1]].x_word_off == dx &&
+               (int64_t)blocks[ids[j]].y_word_off - (int64_t)blocks[ids[j - 1]].y_word_off == dy)
+          ++j;
+        if (dx < 0) j = i + 1;
+      }
+      // cap the batch so the transform workspace stays bounded (1 GiB)
+      size_t cnt = j - i;
+      if (p == QRNG_PATH_NTT) {
+        NttPlan pl;
+        if (ntt_make_plan(n, m, &pl)) {
+          const uint64_t per = ntt_work_elems(pl, 1) * 4;
+          const size_t cap = per ? std::max<uint64_t>(1, (1ull << 30) / per) : cnt;
+          cnt = std::min(cnt, cap);
+        }
+      }
+      cnt = std::min<size_t>(cnt, 1u << 20);
+      const qrng_block& b0 = blocks[ids[i]];
+      qrng_status st = hash_one(ctx, x_pool + b0.x_word_off, n, sd.ptr, &sd, m,
+                                y_pool + b0.y_word_off, p, s, (int)cnt,
+                                cnt > 1 ? (uint64_t)dx * 64 : 0, cnt > 1 ? (uint64_t)dy * 64 : 0);
+      if (st) return st;
+      i += cnt;
+    }
+  }
+  return QRNG_OK;
+}
+
+}  // extern "C"
