@@ -1,0 +1,285 @@
+#!/usr/bin/env python3
+"""Throughput of the QRNG post-processing hot path on one MI355X.
+
+One step = the whole path over one block of synthetic ADC data:
+  1. histogram of the block's 8-bit samples on the GPU and the min-entropy
+     estimate with the statistical-distance correction (paper Sec. II),
+  2. the output length m from H_modify (Sec. III.B),
+  3. the Toeplitz hash y = T x mod 2 (Sec. III.B) with the registered seed,
+     whose transform-domain copy is prepared once per seed and shape.
+Workload (default): one block of 2^20 Gaussian samples (mean 128, sigma 20)
+= n = 2^23 raw bits, m = 5n/8 = 5242880, seed of n+m-1 uniform bits.
+
+Prints ONE JSON line.  `value` is raw input bits hashed per second (Gbit/s)
+with inputs resident in HBM.  `roofline` describes the kernel that takes the
+most device time inside the timed region (timed there with HIP events on its
+own stream); `cpu_baseline` times the CPU oracle on a bounded sample of the
+same block.  Usage: python bench.py [--steps K] [--warmup W] [--path ntt|direct]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+P_NTT = 998244353
+PEAK_INT32_MUL = 39.3e12     # 256 CU x 64 lanes/clk x 2.4 GHz, full-rate v_mul_lo/hi_u32
+PEAK_BITOP = 78.6e12         # 2 x the above: simple 32-bit logic ops dual-issue (cf. fp32 157.3 TFLOP/s)
+PEAK_HBM = 8.0e12
+
+
+def log2i(v):
+    return int(v).bit_length() - 1
+
+
+def ntt_plan(n, m):
+    """Mirror of the library's plan: transform length and four-step split."""
+    L = n + m - 1
+    if L <= (1 << 23):
+        k = max(10, (L - 1).bit_length())
+        nx = ny = 1
+    else:
+        k = 23
+        B = 1 << 22
+        nx, ny = -(-n // B), -(-m // B)
+    if k <= 14:
+        l1, l2 = 0, k
+    else:
+        l2 = min(14, max(10, k - 9))
+        l1 = k - l2
+    return {"log_nc": k, "log1": l1, "log2": l2, "nx": nx, "ny": ny, "nwin": nx + ny - 1}
+
+
+def radix2_modmuls(N):
+    """Non-trivial twiddle products of a radix-2 transform of length N."""
+    if N < 2:
+        return 0
+    return (N // 2) * log2i(N) - (N - 1)
+
+
+def algorithmic_work(kernel, n, m, batch=1):
+    """(amount, unit) of algorithmic work of one launch of `kernel`.
+
+    NTT kernels: modular multiplications of the radix-2 algorithm -- the
+    sub-transforms the kernel performs, the four-step twiddles (column
+    passes) and the pointwise seed products (row pass); each needs at least
+    three 32-bit integer multiplies (Shoup's method).  Direct kernel: m*n
+    GF(2) multiply-adds.  Histogram: sample bytes read.
+    """
+    if kernel.startswith("ntt"):
+        p = ntt_plan(n, m)
+        Nc, N1, N2 = 1 << p["log_nc"], 1 << p["log1"], 1 << p["log2"]
+        twid = Nc - N1 - N2 + 1
+        if kernel == "ntt_rows_hash":
+            mm = (p["nx"] + p["ny"]) * N1 * radix2_modmuls(N2) + p["nx"] * p["ny"] * Nc
+            return 3 * mm * batch, "int32 mul"
+        if kernel == "ntt_cols_fwd":
+            return 3 * p["nx"] * batch * (N2 * radix2_modmuls(N1) + twid), "int32 mul"
+        if kernel == "ntt_cols_inv":
+            return 3 * p["ny"] * batch * (N2 * radix2_modmuls(N1) + twid), "int32 mul"
+        if kernel == "ntt_fused_hash":
+            return 3 * batch * (2 * radix2_modmuls(Nc) + Nc), "int32 mul"
+        if kernel in ("ntt_rows_seed", "ntt_fused_seed"):
+            return 3 * p["nwin"] * (N1 * radix2_modmuls(N2) + Nc), "int32 mul"
+    if kernel == "direct":
+        return m * n * batch, "GF(2) MAC"
+    if kernel == "histogram":
+        return n // 8, "byte"
+    return None, None
+
+
+def roofline_for(kernel, work, unit, avg_s, traffic):
+    if unit == "int32 mul":
+        achieved = work / avg_s / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_INT32_MUL / 1e12,
+                "unit": "T int32-mul/s", "frac": round(achieved * 1e12 / PEAK_INT32_MUL, 4),
+                "traffic": traffic, "kernel": kernel}
+    if unit == "GF(2) MAC":
+        achieved = work / 32.0 / avg_s / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_BITOP / 1e12,
+                "unit": "T bitop/s (32 GF(2) MAC each)",
+                "frac": round(achieved * 1e12 / PEAK_BITOP, 4), "traffic": traffic,
+                "kernel": kernel}
+    achieved = work / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": round(achieved * 1e9 / PEAK_HBM, 4), "traffic": traffic,
+            "kernel": kernel}
+
+
+def source_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2011_04130_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("source_digest") != source_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(xw, n, sw, m, seconds=12.0):
+    """The oracle (packed C evaluation of k = T r, OpenMP) on a bounded row
+    sample of the same block, scaled by m / rows to the whole block."""
+    import numpy as np
+    import oracle
+    L = n + m - 1
+    rows_done, t_used, chunk = 0, 0.0, 256
+    while t_used < seconds and rows_done < m:
+        r = np.arange(rows_done, min(m, rows_done + chunk), dtype=np.uint64)
+        t0 = time.perf_counter()
+        oracle.toeplitz_rows(xw, n, sw, L, r)
+        t_used += time.perf_counter() - t0
+        rows_done += len(r)
+        chunk = min(chunk * 2, 1 << 16)
+    full_s = t_used * m / rows_done
+    return {"value": round(n / full_s / 1e9, 6), "unit": "Gbit/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "rows 0..%d of the %d-row block (packed C oracle), %.1f s, scaled by m/rows"
+                      % (rows_done - 1, m, t_used)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--path", choices=["ntt", "direct"], default="ntt")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="oracle time budget for cpu_baseline (0 = skip)")
+    ap.add_argument("--extras", type=int, default=1, help="also time the other paths")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 26, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "launches": 5}))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2011_04130_amd as q
+    import qrng_inputs as qi
+
+    cfg = qi.config(1)
+    n, S = cfg["n"], cfg["S"]
+    samples = qi.gen_adc(S, cfg["sigma"], seed=cfg["adc_seed"])
+    xw = qi.samples_as_words(samples)
+    m_expect = cfg["m_expected"]
+    sw = qi.gen_seed_words(n + m_expect - 1, cfg["seed_seed"])
+    dev = "cuda:0"
+    s_t = torch.from_numpy(samples).to(dev)
+    x_t = torch.from_numpy(xw.view(np.int64).copy()).to(dev)
+    seed_t = torch.from_numpy(sw.view(np.int64).copy()).to(dev)
+    y_t = torch.empty((m_expect + 63) // 64, dtype=torch.int64, device=dev)
+    path = q.PATH_NTT if args.path == "ntt" else q.PATH_DIRECT
+
+    ctx = q.Context(0)
+    sid = ctx.register_seed(seed_t, n + m_expect - 1)
+
+    def step():
+        me = ctx.minentropy(s_t)
+        m = q.output_bits(n, 8, me["h_mod"])
+        ctx.hash_seeded(x_t, n, sid, m, y=y_t, path=path)
+        return m
+
+    for _ in range(args.warmup):
+        m = step()
+    assert m == m_expect, "min-entropy gave m=%d, expected %d" % (m, m_expect)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_step = elapsed / args.steps * 1e3
+    value = n / (elapsed / args.steps) / 1e9
+
+    kernels = {k: {"launches": c, "avg_us": round(ms / c * 1e3, 3)} for k, (c, ms) in prof.items()}
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    cnt, tot_ms = prof[dom]
+    avg_s = tot_ms / cnt / 1e3
+    work, unit = algorithmic_work(dom, n if dom != "histogram" else S * 8, m)
+    roof = roofline_for(dom, work, unit, avg_s, measured_traffic(dom, cfg["name"]))
+    roof["avg_us"] = round(avg_s * 1e6, 3)
+
+    out = {
+        "metric": "raw Gbit/s hashed bit-exact (one block, min-entropy + Toeplitz hash)",
+        "value": round(value, 4),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if path == q.PATH_NTT else "u32 (bit-packed)",
+        "data": "synthetic (seeded Gaussian 8-bit ADC samples, uniform seed)",
+        "config": {"workload": cfg["name"], "n": n, "m": m, "samples": S,
+                   "path": args.path, "seed": "registered; transform prepared once"},
+        "extracted_gbps": round(m / (elapsed / args.steps) / 1e9, 4),
+        "kernels": kernels,
+        "roofline": roof,
+    }
+
+    if args.extras:
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps
+
+        t_plain = timed(lambda: ctx.hash(x_t, n, seed_t, m, y=y_t, path=q.PATH_NTT), 10)
+        t_seeded = timed(lambda: ctx.hash_seeded(x_t, n, sid, m, y=y_t, path=q.PATH_NTT), 20)
+        t_direct = timed(lambda: ctx.hash_seeded(x_t, n, sid, m, y=y_t, path=q.PATH_DIRECT), 2)
+        out["hash_only_gbps"] = {
+            "ntt_registered_seed": round(n / t_seeded / 1e9, 3),
+            "ntt_seed_transformed_each_call": round(n / t_plain / 1e9, 3),
+            "direct": round(n / t_direct / 1e9, 4)}
+
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(xw, n, sw, m, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

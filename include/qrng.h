@@ -160,6 +160,22 @@ qrng_status qrng_toeplitz_hash_batched(qrng_ctx *ctx, const qrng_block *blocks_h
                                        uint32_t nblocks, const uint64_t *x_pool_dev,
                                        uint64_t *y_pool_dev, int path, void *stream);
 
+/* Measurement aid.  While enabled, every kernel the context launches is
+ * bracketed by HIP events recorded on the stream it runs on (a few
+ * microseconds of host overhead per launch; results are unchanged). */
+qrng_status qrng_profile_enable(qrng_ctx *ctx, int on);
+
+/* Name of kernel class `kernel_id` (0, 1, ...), NULL past the last class. */
+const char *qrng_profile_kernel_name(int kernel_id);
+
+/* Launch count and summed device time (ms) of one kernel class since the
+ * last reset.  Waits for the recorded events. */
+qrng_status qrng_profile_query(qrng_ctx *ctx, int kernel_id, uint64_t *launches,
+                               double *total_ms);
+
+/* Forget the recorded launches (waits for them first). */
+qrng_status qrng_profile_reset(qrng_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

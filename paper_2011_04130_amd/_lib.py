@@ -51,7 +51,8 @@ _lib = None
 EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
-           "qrng_toeplitz_hash_batched"]
+           "qrng_toeplitz_hash_batched", "qrng_profile_enable", "qrng_profile_kernel_name",
+           "qrng_profile_query", "qrng_profile_reset"]
 
 
 def load_library(path: str | None = None):
@@ -87,6 +88,15 @@ def load_library(path: str | None = None):
     lib.qrng_toeplitz_hash_batched.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp,
                                                i32, vp]
     lib.qrng_toeplitz_hash_batched.restype = i32
+    lib.qrng_profile_enable.argtypes = [vp, i32]
+    lib.qrng_profile_enable.restype = i32
+    lib.qrng_profile_kernel_name.argtypes = [i32]
+    lib.qrng_profile_kernel_name.restype = ctypes.c_char_p
+    lib.qrng_profile_query.argtypes = [vp, i32, ctypes.POINTER(u64),
+                                       ctypes.POINTER(ctypes.c_double)]
+    lib.qrng_profile_query.restype = i32
+    lib.qrng_profile_reset.argtypes = [vp]
+    lib.qrng_profile_reset.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -96,6 +106,18 @@ def check(status: int) -> None:
     if status != OK:
         msg = load_library().qrng_last_error().decode(errors="replace")
         raise QrngError(status, msg)
+
+
+def kernel_names() -> list:
+    """Kernel classes the timing hooks report, in id order."""
+    lib = load_library()
+    out, i = [], 0
+    while True:
+        nm = lib.qrng_profile_kernel_name(i)
+        if not nm:
+            return out
+        out.append(nm.decode())
+        i += 1
 
 
 def version() -> str:

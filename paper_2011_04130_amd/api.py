@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, U_MODEL_ARGMAX, Block, MeOpts, MeResult,
-                   QrngError, check, load_library)
+                   QrngError, check, kernel_names, load_library)
 
 
 def _words(bits: int) -> int:
@@ -77,6 +77,24 @@ class Context:
         if y.numel() * y.element_size() < _words(m) * 8:
             raise ValueError("output buffer too small for %d bits" % m)
         return y
+
+    # -- kernel timing --------------------------------------------------------
+    def profile(self, on: bool = True) -> None:
+        """Bracket every kernel launch with HIP events on its own stream."""
+        check(self._lib.qrng_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self) -> None:
+        check(self._lib.qrng_profile_reset(self._h))
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total_ms)} since the last reset."""
+        out = {}
+        for kid, name in enumerate(kernel_names()):
+            cnt, ms = ctypes.c_uint64(), ctypes.c_double()
+            check(self._lib.qrng_profile_query(self._h, kid, ctypes.byref(cnt), ctypes.byref(ms)))
+            if cnt.value:
+                out[name] = (int(cnt.value), float(ms.value))
+        return out
 
     # -- Sec. II ------------------------------------------------------------
     def minentropy(self, samples, sample_bits: int = 8, model: int = MODEL_FIT,

@@ -123,11 +123,13 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
   const uint64_t nsw = (L + 31) / 32;  // seed words holding bits < L
   const uint64_t ywords = 2 * ((m + 63) / 64);
   const uint32_t nbz = (uint32_t)((ywords + 255) / 256);
+  prof_begin(KID_DIRECT_PREP, s);
   hipLaunchKernelGGL(k_zero, dim3(nbz * (uint32_t)batch), dim3(256), 0, s, y_bits, ywords,
                      y_stride_bits / 32, nbz);
   const uint32_t nbr = (uint32_t)((W + 255) / 256);
   hipLaunchKernelGGL(k_reverse, dim3(nbr * (uint32_t)batch), dim3(256), 0, s, x_bits, n,
                      x_stride_bits / 32, work, W, nbr);
+  prof_end(KID_DIRECT_PREP, s);
   const uint64_t G = (m + 31) / 32;
   const uint32_t nrb = (uint32_t)((G + 63) / 64);
   // split the W+1 seed-word offsets so that the launch holds enough waves
@@ -139,8 +141,10 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
   uint64_t uchunk = (W + 1 + nchunk - 1) / nchunk;
   if (uchunk < 64) uchunk = 64;
   nchunk = (W + 1 + uchunk - 1) / uchunk;
+  prof_begin(KID_DIRECT, s);
   hipLaunchKernelGGL(k_direct, dim3(nrb * (uint32_t)batch, (uint32_t)nchunk), dim3(64), 0, s,
                      seed_bits, nsw, work, W, m, uchunk, y_bits, y_stride_bits / 32, nrb);
+  prof_end(KID_DIRECT, s);
   return hipGetLastError();
 }
 

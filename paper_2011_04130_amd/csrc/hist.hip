@@ -70,7 +70,9 @@ hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
   const uint64_t cap = (uint64_t)num_cus * 8;
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
+  prof_begin(KID_HIST, s);
   hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), 0, s, samples, S, nbins, counts);
+  prof_end(KID_HIST, s);
   return hipGetLastError();
 }
 

@@ -5,6 +5,27 @@
 
 namespace qrng {
 
+// ------------------------------------------------------- kernel timing hooks
+// Every launch site brackets its kernel with prof_begin/prof_end.  They are
+// no-ops unless the calling thread's context has timing enabled, in which
+// case HIP events are recorded on the launch stream.
+enum KernelId {
+  KID_COLS_FWD = 0,   // four-step pass A (raw block or seed window columns)
+  KID_ROWS_HASH,      // pass B: row transforms, seed product, inverse rows
+  KID_ROWS_SEED,      // pass B for a seed window (forward only)
+  KID_COLS_INV,       // pass C: inverse columns and bit packing
+  KID_FUSED_HASH,     // whole transform in one kernel (Nc <= 2^14)
+  KID_FUSED_SEED,
+  KID_DIRECT,         // bit-packed direct product
+  KID_DIRECT_PREP,    // output clear and raw-block reversal
+  KID_HIST,           // sample histogram
+  KID_MFMA,           // int8 matrix-core product
+  KID_COUNT
+};
+const char* kernel_name(int kid);
+void prof_begin(int kid, hipStream_t s);
+void prof_end(int kid, hipStream_t s);
+
 // ---------------------------------------------------------------- NTT path
 // Per-sub-length twiddle tables (w, floor(w 2^32/p)) and the two-level
 // Montgomery table of the 2^23-rd root used by the four-step twiddles.

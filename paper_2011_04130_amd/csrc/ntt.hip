@@ -404,12 +404,16 @@ __global__ __launch_bounds__((1 << LOG2) / 16) void k_rows(RowArgs a, TwTables t
 // ------------------------------------------------------------ dispatch
 template <int LOG1>
 hipError_t launch_cols_fwd(const ColFwdArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
+  prof_begin(KID_COLS_FWD, s);
   hipLaunchKernelGGL(k_cols_fwd<LOG1>, grid, dim3(256), 0, s, a, tw);
+  prof_end(KID_COLS_FWD, s);
   return hipGetLastError();
 }
 template <int LOG1>
 hipError_t launch_cols_inv(const ColInvArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
+  prof_begin(KID_COLS_INV, s);
   hipLaunchKernelGGL(k_cols_inv<LOG1>, grid, dim3(256), 0, s, a, tw);
+  prof_end(KID_COLS_INV, s);
   return hipGetLastError();
 }
 
@@ -446,8 +450,12 @@ hipError_t cols_inv(int log1, const ColInvArgs& a, dim3 grid, const TwTables& tw
 
 template <int LOG2, int NX, bool IN_BITS, bool SEED, bool OUT_BITS>
 hipError_t launch_rows(const RowArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
+  constexpr int kid = IN_BITS ? (SEED ? KID_FUSED_SEED : KID_FUSED_HASH)
+                              : (SEED ? KID_ROWS_SEED : KID_ROWS_HASH);
+  prof_begin(kid, s);
   hipLaunchKernelGGL((k_rows<LOG2, NX, IN_BITS, SEED, OUT_BITS>), grid, dim3((1 << LOG2) / 16),
                      0, s, a, tw);
+  prof_end(kid, s);
   return hipGetLastError();
 }
 

@@ -19,6 +19,16 @@
 
 using namespace qrng;
 
+namespace qrng {
+const char* kernel_name(int kid) {
+  static const char* names[KID_COUNT] = {"ntt_cols_fwd", "ntt_rows_hash", "ntt_rows_seed",
+                                         "ntt_cols_inv", "ntt_fused_hash", "ntt_fused_seed",
+                                         "direct",       "direct_prep",   "histogram",
+                                         "mfma"};
+  return (kid >= 0 && kid < KID_COUNT) ? names[kid] : nullptr;
+}
+}  // namespace qrng
+
 namespace {
 
 thread_local std::string g_err;
@@ -71,8 +81,18 @@ struct DeviceGuard {
 
 }  // namespace
 
+struct ProfRec {
+  int kid;
+  hipEvent_t a, b;
+};
+
 struct qrng_ctx {
   int device = 0;
+  // kernel timing (measurement aid)
+  bool prof_on = false;
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+  hipEvent_t prof_open = nullptr;
   int num_cus = 256;
   uint2* tw_fwd = nullptr;
   uint2* tw_inv = nullptr;
@@ -88,6 +108,35 @@ struct qrng_ctx {
 };
 
 namespace {
+
+thread_local qrng_ctx* t_ctx = nullptr;
+
+// Makes `c` the context whose timing hooks the kernel launches of this
+// thread report to, for the duration of one C-ABI call.
+struct CtxScope {
+  qrng_ctx* prev;
+  explicit CtxScope(qrng_ctx* c) : prev(t_ctx) { t_ctx = c; }
+  ~CtxScope() { t_ctx = prev; }
+};
+
+hipEvent_t prof_event(qrng_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_release(qrng_ctx* c) {
+  for (auto& r : c->prof_recs) {
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_recs.clear();
+}
 
 qrng_status ensure_work(qrng_ctx* c, uint64_t words) {
   if (words <= c->work_words) return QRNG_OK;
@@ -278,7 +327,71 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
 
 }  // namespace
 
+namespace qrng {
+void prof_begin(int kid, hipStream_t s) {
+  qrng_ctx* c = t_ctx;
+  if (!c || !c->prof_on) return;
+  hipEvent_t e = prof_event(c);
+  if (e && hipEventRecord(e, s) == hipSuccess) {
+    c->prof_open = e;
+  } else {
+    if (e) c->prof_pool.push_back(e);
+    c->prof_open = nullptr;
+  }
+  (void)kid;
+}
+void prof_end(int kid, hipStream_t s) {
+  qrng_ctx* c = t_ctx;
+  if (!c || !c->prof_on || !c->prof_open) return;
+  hipEvent_t e = prof_event(c);
+  if (e && hipEventRecord(e, s) == hipSuccess) {
+    c->prof_recs.push_back(ProfRec{kid, c->prof_open, e});
+  } else {
+    c->prof_pool.push_back(c->prof_open);
+    if (e) c->prof_pool.push_back(e);
+  }
+  c->prof_open = nullptr;
+}
+}  // namespace qrng
+
 extern "C" {
+
+qrng_status qrng_profile_enable(qrng_ctx* ctx, int on) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  ctx->prof_on = on != 0;
+  return QRNG_OK;
+}
+
+const char* qrng_profile_kernel_name(int kernel_id) { return kernel_name(kernel_id); }
+
+qrng_status qrng_profile_query(qrng_ctx* ctx, int kernel_id, uint64_t* launches,
+                               double* total_ms) {
+  if (!ctx || !launches || !total_ms) return fail(QRNG_EINVAL, "null argument");
+  if (!kernel_name(kernel_id)) return fail(QRNG_EINVAL, "unknown kernel id %d", kernel_id);
+  DeviceGuard g(ctx->device);
+  uint64_t cnt = 0;
+  double tot = 0.0;
+  for (auto& r : ctx->prof_recs) {
+    if (r.kid != kernel_id) continue;
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    ++cnt;
+    tot += ms;
+  }
+  *launches = cnt;
+  *total_ms = tot;
+  return QRNG_OK;
+}
+
+qrng_status qrng_profile_reset(qrng_ctx* ctx) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  DeviceGuard g(ctx->device);
+  for (auto& r : ctx->prof_recs) HIP_TRY(hipEventSynchronize(r.b));
+  prof_release(ctx);
+  return QRNG_OK;
+}
+
 
 const char* qrng_version(void) { return "libqrng 0.1 (gfx950)"; }
 
@@ -326,6 +439,8 @@ void qrng_destroy(qrng_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& kv : c->seeds)
     for (auto& sp : kv.second.spectra) (void)hipFree(sp.second);
+  prof_release(c);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->tw_fwd) (void)hipFree(c->tw_fwd);
   if (c->tw_inv) (void)hipFree(c->tw_inv);
   if (c->g_lo) (void)hipFree(c->g_lo);
@@ -369,6 +484,7 @@ qrng_status qrng_minentropy(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
       !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
     return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
   DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int K = 1 << N;
   HIP_TRY(histogram_u8(samples, S, K, ctx->counts_dev, ctx->num_cus, s));
@@ -388,6 +504,7 @@ qrng_status qrng_toeplitz_hash(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
   qrng_status st = check_hash_args(ctx, x, n, seed, m, y, path);
   if (st || m == 0) return st;
   DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
   return hash_one(ctx, x, n, seed, nullptr, m, y, path, reinterpret_cast<hipStream_t>(stream),
                   1, 0, 0);
 }
@@ -427,6 +544,7 @@ qrng_status qrng_toeplitz_hash_seeded(qrng_ctx* ctx, const uint64_t* x, uint64_t
     return fail(QRNG_EINVAL, "seed has %llu bits, block needs %llu", (unsigned long long)sd.L,
                 (unsigned long long)(n + m - 1));
   DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
   return hash_one(ctx, x, n, sd.ptr, &sd, m, y, path, reinterpret_cast<hipStream_t>(stream), 1,
                   0, 0);
 }
@@ -456,6 +574,7 @@ qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
   for (size_t i = 1; i < yr.size(); ++i)
     if (yr[i].first < yr[i - 1].second) return fail(QRNG_EINVAL, "output ranges overlap");
   DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   // group equal shapes whose offsets advance by constant strides: one launch each
   std::map<std::tuple<uint64_t, uint64_t, uint32_t>, std::vector<uint32_t>> groups;
