@@ -65,7 +65,7 @@ struct RP {
 };
 
 // Round k works on sub-arrays of length R = r * s; group g = (sub, b) owns the
-// r elements sub*R + a*s + b.
+// r elements sub*R + a*s + b, a < r.
 template <int LOG, int k>
 struct Geo {
   static constexpr int lgr = RP<LOG>::lgr(k), r = 1 << lgr;
@@ -73,9 +73,10 @@ struct Geo {
   static constexpr int s = R / r;
   static constexpr int groups = (1 << LOG) / r;
   static constexpr int toff = tw_off(lgR, lgr);
-  __device__ static __forceinline__ int pos(int g, int a) {
-    return (g / s) * R + a * s + (g % s);
-  }
+  // stride between consecutive a in the padded row layout (one pad word per
+  // 16): linear because every round of a row has s == 1 or s % 16 == 0
+  static constexpr int SP = s >= 16 ? s + s / 16 : 1;
+  __device__ static __forceinline__ int pos0(int g) { return (g / s) * R + (g % s); }
 };
 
 template <int B, int E, class F>
@@ -94,46 +95,64 @@ __device__ __forceinline__ void static_for_down(F&& f) {
   }
 }
 
-// Forward round on group g: load, radix-r DIF, twiddle w_R^(b bitrev(a')), store.
-template <int LOG, int k, class LD, class ST>
-__device__ __forceinline__ void fwd_group(int g, const uint2* __restrict__ twf, LD&& ld,
-                                          ST&& st) {
+// One round on GPT groups g0 + u*gstep.  All loads are issued before any
+// butterfly and all stores after, so the groups' arithmetic interleaves and
+// hides load latency.  Forward: radix-r DIF then twiddle w_R^(b bitrev(a'));
+// inverse: twiddle w_R^-(b bitrev(a')) then radix-r DIT.
+// ld(g, a) / st(g, a, v) address element a of group g.
+template <int LOG, int k, int GPT, bool INV, class LD, class ST>
+__device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __restrict__ tws,
+                                            LD&& ld, ST&& st) {
   using G = Geo<LOG, k>;
-  uint32_t v[G::r];
+  uint32_t v[GPT][G::r];
 #pragma unroll
-  for (int a = 0; a < G::r; ++a) v[a] = ld(G::pos(g, a));
-  dft_reg<G::r, false>(v);
-  if constexpr (G::s > 1) {
-    const uint2* T = twf + G::toff + (g % G::s) * G::r;
+  for (int u = 0; u < GPT; ++u)
 #pragma unroll
-    for (int a = 1; a < G::r; ++a) {
-      uint2 t = T[a];
-      v[a] = mul_shoup(v[a], t.x, t.y);
+    for (int a = 0; a < G::r; ++a) v[u][a] = ld(g0 + u * gstep, a);
+#pragma unroll
+  for (int u = 0; u < GPT; ++u) {
+    if constexpr (INV) {
+      if constexpr (G::s > 1) {
+        const uint2* T = tws + G::toff + ((g0 + u * gstep) % G::s) * G::r;
+#pragma unroll
+        for (int a = 1; a < G::r; ++a) {
+          const uint2 t = T[a];
+          v[u][a] = mul_shoup(v[u][a], t.x, t.y);
+        }
+      }
+      dft_reg<G::r, true>(v[u]);
+    } else {
+      dft_reg<G::r, false>(v[u]);
+      if constexpr (G::s > 1) {
+        const uint2* T = tws + G::toff + ((g0 + u * gstep) % G::s) * G::r;
+#pragma unroll
+        for (int a = 1; a < G::r; ++a) {
+          const uint2 t = T[a];
+          v[u][a] = mul_shoup(v[u][a], t.x, t.y);
+        }
+      }
     }
   }
 #pragma unroll
-  for (int a = 0; a < G::r; ++a) st(G::pos(g, a), v[a]);
+  for (int u = 0; u < GPT; ++u)
+#pragma unroll
+    for (int a = 0; a < G::r; ++a) st(g0 + u * gstep, a, v[u][a]);
 }
 
-// Inverse round on group g: load, twiddle w_R^-(b bitrev(a')), radix-r DIT, store.
-template <int LOG, int k, class LD, class ST>
-__device__ __forceinline__ void inv_group(int g, const uint2* __restrict__ twi, LD&& ld,
-                                          ST&& st) {
-  using G = Geo<LOG, k>;
-  uint32_t v[G::r];
-#pragma unroll
-  for (int a = 0; a < G::r; ++a) v[a] = ld(G::pos(g, a));
-  if constexpr (G::s > 1) {
-    const uint2* T = twi + G::toff + (g % G::s) * G::r;
-#pragma unroll
-    for (int a = 1; a < G::r; ++a) {
-      uint2 t = T[a];
-      v[a] = mul_shoup(v[a], t.x, t.y);
-    }
+// Every group of round k, NT threads (this thread = t), at most GMAX groups
+// in flight per thread.
+template <int LOG, int k, int NT, int GMAX, bool INV, class LD, class ST>
+__device__ __forceinline__ void round_all(int t, const uint2* __restrict__ tws, LD&& ld, ST&& st) {
+  constexpr int groups = Geo<LOG, k>::groups;
+  if constexpr (groups >= NT) {
+    constexpr int per = groups / NT;
+    constexpr int gpt = per < GMAX ? per : GMAX;
+#pragma unroll 1
+    for (int it = 0; it < per / gpt; ++it)
+      round_multi<LOG, k, gpt, INV>(t + it * gpt * NT, NT, tws, ld, st);
+  } else {
+    if (t < groups) round_multi<LOG, k, 1, INV>(t, NT, tws, ld, st);
   }
-  dft_reg<G::r, true>(v);
-#pragma unroll
-  for (int a = 0; a < G::r; ++a) st(G::pos(g, a), v[a]);
 }
 
 // w_{2^23}^e in Montgomery form
@@ -147,68 +166,79 @@ __device__ __forceinline__ int brev(int p) {
 }
 
 // Transform position q of an item maps to bit off + (q < h ? q : q - Nc) of
-// the source, or to 0 when that index falls outside [lo, hi).
+// the source, or to 0 when that index falls outside [lo, hi).  All indices
+// fit 32 bits: the NTT path takes n < p < 2^30, so n+m-1 < 2^31.
 struct BitMap {
-  int64_t off, lo, hi, h;
+  int32_t off, lo, hi, h;
 };
 constexpr int MAXMAP = 8;
 
 __device__ __forceinline__ uint32_t map_bit(const uint32_t* __restrict__ bits, const BitMap& mp,
-                                            int64_t q, int64_t Nc, uint64_t zo) {
-  int64_t k = q < mp.h ? q : q - Nc;
-  int64_t idx = mp.off + k;
-  if (idx < mp.lo || idx >= mp.hi) return 0u;
-  return get_bit(bits, (uint64_t)idx + zo);
+                                            int32_t q, int32_t Nc) {
+  const int32_t idx = mp.off + (q < mp.h ? q : q - Nc);
+  if ((uint32_t)(idx - mp.lo) >= (uint32_t)(mp.hi - mp.lo)) return 0u;
+  return (bits[(uint32_t)idx >> 5] >> (idx & 31)) & 1u;
 }
 
 // ----------------------------------------------------------------- pass A
 struct ColFwdArgs {
   const uint32_t* bits;
-  uint64_t zs;  // batch stride of the bit source
+  uint64_t zs;  // batch stride of the bit source (bits, multiple of 32)
   BitMap map[MAXMAP];
   int nmap;
   int log2, log_nc;
   uint32_t* out;  // item y = blockIdx.y at out + y * Nc
 };
 
-constexpr int COLS = 32;   // columns per workgroup
-constexpr int CSLOTS = 8;  // 256 threads = 32 columns x 8 slots
+constexpr int COLS = 32;    // columns per workgroup (128-byte rows)
+constexpr int CSLOTS = 16;  // 512 threads = 32 columns x 16 slots
+constexpr int CGMAX = 2;    // groups in flight per thread
 
 template <int LOG1>
-__global__ __launch_bounds__(256) void k_cols_fwd(ColFwdArgs a, TwTables tw) {
+__global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTables tw) {
   __shared__ uint32_t lds[(1 << LOG1) * COLS];
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
-  const int64_t Nc = (int64_t)1 << a.log_nc;
+  const int32_t Nc = 1 << a.log_nc;
   const int j2 = blockIdx.x * COLS + c;
   const int mi = blockIdx.y % a.nmap;
-  const uint64_t zo = (uint64_t)(blockIdx.y / a.nmap) * a.zs;
+  const uint32_t* __restrict__ bits = a.bits + (uint64_t)(blockIdx.y / a.nmap) * (a.zs >> 5);
   const BitMap mp = a.map[mi];
-  uint32_t* __restrict__ out = a.out + (uint64_t)blockIdx.y * Nc;
+  uint32_t* __restrict__ out = a.out + (uint64_t)blockIdx.y * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
+  const int l2 = a.log2;
 
-  auto ld_bits = [&](int j1) -> uint32_t {
-    return map_bit(a.bits, mp, ((int64_t)j1 << a.log2) + j2, Nc, zo);
+  auto ld_bits = [&](int g, int e) -> uint32_t {
+    const int j1 = Geo<LOG1, 0>::pos0(g) + e * Geo<LOG1, 0>::s;
+    return map_bit(bits, mp, (j1 << l2) + j2, Nc);
   };
-  auto ld_lds = [&](int j1) -> uint32_t { return lds[j1 * COLS + c]; };
-  auto st_lds = [&](int j1, uint32_t v) { lds[j1 * COLS + c] = v; };
-  auto st_out = [&](int p, uint32_t v) {
-    uint32_t e = gstep * (uint32_t)brev<LOG1>(p);
-    out[((int64_t)p << a.log2) + j2] = mul_mont(v, gtw(tw, e));
+  auto ld_lds_k = [&](auto kc) {
+    return [&](int g, int e) -> uint32_t {
+      using G = Geo<LOG1, decltype(kc)::value>;
+      return lds[(G::pos0(g) + e * G::s) * COLS + c];
+    };
+  };
+  auto st_lds_k = [&](auto kc) {
+    return [&](int g, int e, uint32_t v) {
+      using G = Geo<LOG1, decltype(kc)::value>;
+      lds[(G::pos0(g) + e * G::s) * COLS + c] = v;
+    };
   };
   constexpr int K = RP<LOG1>::K;
+  auto st_out = [&](int g, int e, uint32_t v) {
+    const int p = Geo<LOG1, K - 1>::pos0(g) + e * Geo<LOG1, K - 1>::s;
+    const uint32_t ex = gstep * (uint32_t)brev<LOG1>(p);
+    out[((uint32_t)p << l2) + j2] = mul_mont(v, gtw(tw, ex));
+  };
   static_for<0, K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    using G = Geo<LOG1, k>;
-    for (int g = slot; g < G::groups; g += CSLOTS) {
-      if constexpr (K == 1)
-        fwd_group<LOG1, k>(g, tw.fwd, ld_bits, st_out);
-      else if constexpr (k == 0)
-        fwd_group<LOG1, k>(g, tw.fwd, ld_bits, st_lds);
-      else if constexpr (k == K - 1)
-        fwd_group<LOG1, k>(g, tw.fwd, ld_lds, st_out);
-      else
-        fwd_group<LOG1, k>(g, tw.fwd, ld_lds, st_lds);
-    }
+    if constexpr (K == 1)
+      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_bits, st_out);
+    else if constexpr (k == 0)
+      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_bits, st_lds_k(kc));
+    else if constexpr (k == K - 1)
+      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_out);
+    else
+      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k < K - 1) __syncthreads();
   });
 }
@@ -224,49 +254,61 @@ struct ColInvArgs {
 };
 
 template <int LOG1>
-__global__ __launch_bounds__(256) void k_cols_inv(ColInvArgs a, TwTables tw) {
+__global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTables tw) {
   __shared__ uint32_t lds[(1 << LOG1) * COLS];
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int lane = threadIdx.x & 63;
-  const int64_t Nc = (int64_t)1 << a.log_nc;
+  const int32_t Nc = 1 << a.log_nc;
   const int j2 = blockIdx.x * COLS + c;
   const int o = blockIdx.y % a.ny;
   const uint64_t ybase = (uint64_t)(blockIdx.y / a.ny) * a.y_zs + (uint64_t)o * a.by;
   const int64_t rem = (int64_t)a.m - (int64_t)o * a.by;
-  const int64_t yvalid = rem < a.by ? rem : a.by;
-  const int64_t ylimit = (yvalid + 63) & ~(int64_t)63;
-  const uint32_t* __restrict__ in = a.in + (uint64_t)blockIdx.y * Nc;
+  const int32_t yvalid = (int32_t)(rem < a.by ? rem : a.by);
+  const int32_t ylimit = (yvalid + 63) & ~63;
+  uint32_t* __restrict__ ywords = a.y + (ybase >> 5);
+  const uint32_t* __restrict__ in = a.in + (uint64_t)blockIdx.y * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   constexpr uint32_t EMASK = (1u << LOG_MAX) - 1;
+  const int l2 = a.log2;
+  constexpr int K = RP<LOG1>::K;
 
-  auto ld_in = [&](int p) -> uint32_t {
-    uint32_t e = (0u - gstep * (uint32_t)brev<LOG1>(p)) & EMASK;
-    return mul_mont(in[((int64_t)p << a.log2) + j2], gtw(tw, e));
+  auto ld_in = [&](int g, int e) -> uint32_t {
+    const int p = Geo<LOG1, K - 1>::pos0(g) + e * Geo<LOG1, K - 1>::s;
+    const uint32_t ex = (0u - gstep * (uint32_t)brev<LOG1>(p)) & EMASK;
+    return mul_mont(in[((uint32_t)p << l2) + j2], gtw(tw, ex));
   };
-  auto ld_lds = [&](int j1) -> uint32_t { return lds[j1 * COLS + c]; };
-  auto st_lds = [&](int j1, uint32_t v) { lds[j1 * COLS + c] = v; };
-  auto st_bits = [&](int j1, uint32_t v) {
-    const int64_t t = ((int64_t)j1 << a.log2) + j2;
+  auto ld_lds_k = [&](auto kc) {
+    return [&](int g, int e) -> uint32_t {
+      using G = Geo<LOG1, decltype(kc)::value>;
+      return lds[(G::pos0(g) + e * G::s) * COLS + c];
+    };
+  };
+  auto st_lds_k = [&](auto kc) {
+    return [&](int g, int e, uint32_t v) {
+      using G = Geo<LOG1, decltype(kc)::value>;
+      lds[(G::pos0(g) + e * G::s) * COLS + c] = v;
+    };
+  };
+  // natural-order position j1 -> output bit t = j1*N2 + j2; the 32 lanes of
+  // a half-wave hold 32 consecutive bits of one output word
+  auto st_bits = [&](int g, int e, uint32_t v) {
+    const int j1 = Geo<LOG1, 0>::pos0(g) + e * Geo<LOG1, 0>::s;
+    const int32_t t = (j1 << l2) + j2;
     const uint32_t bit = (t < yvalid) ? (red1(v) & 1u) : 0u;
     const uint64_t bal = __ballot(bit);
-    const int64_t t0 = t - c;  // first column of this half-wave
-    if ((lane & 31) == 0 && t0 < ylimit)
-      a.y[(ybase + (uint64_t)t0) >> 5] = lane ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+    const int32_t t0 = t - c;
+    if ((lane & 31) == 0 && t0 < ylimit) ywords[t0 >> 5] = lane ? (uint32_t)(bal >> 32) : (uint32_t)bal;
   };
-  constexpr int K = RP<LOG1>::K;
   static_for_down<0, K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    using G = Geo<LOG1, k>;
-    for (int g = slot; g < G::groups; g += CSLOTS) {
-      if constexpr (K == 1)
-        inv_group<LOG1, k>(g, tw.inv, ld_in, st_bits);
-      else if constexpr (k == K - 1)
-        inv_group<LOG1, k>(g, tw.inv, ld_in, st_lds);
-      else if constexpr (k == 0)
-        inv_group<LOG1, k>(g, tw.inv, ld_lds, st_bits);
-      else
-        inv_group<LOG1, k>(g, tw.inv, ld_lds, st_lds);
-    }
+    if constexpr (K == 1)
+      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_in, st_bits);
+    else if constexpr (k == K - 1)
+      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_in, st_lds_k(kc));
+    else if constexpr (k == 0)
+      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_bits);
+    else
+      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k > 0) __syncthreads();
   });
 }
@@ -275,7 +317,7 @@ __global__ __launch_bounds__(256) void k_cols_inv(ColInvArgs a, TwTables tw) {
 struct RowArgs {
   const uint32_t* in;  // residues (pass-A output); item at in + item * Nc + row * N2
   const uint32_t* bits;
-  uint64_t zs;  // batch stride of the bit source (fused)
+  uint64_t zs;  // batch stride of the bit source (fused; bits, multiple of 32)
   BitMap map[MAXMAP];
   const uint32_t* W;  // seed spectra, window w at W + w * Nc
   int nx, ny, log_nc;
@@ -286,15 +328,23 @@ struct RowArgs {
   uint64_t m;
 };
 
+// Threads of a row kernel: every thread owns GPT groups of the last round.
+template <int LOG2, int GPT>
+constexpr int row_threads() {
+  return (1 << LOG2) / (16 * GPT);
+}
+
 // One row of the four-step (or the whole transform when N1 = 1).
 //  SEED:  forward transform of a seed window -> Montgomery-form spectrum row.
 //  hash:  forward transforms of NX raw chunks, products with the seed
 //         spectra summed per output chunk, inverse transform per output chunk.
 // IN_BITS / OUT_BITS: the row is the whole transform and reads raw bits /
-// writes hash bits directly.
-template <int LOG2, int NX, bool IN_BITS, bool SEED, bool OUT_BITS>
-__global__ __launch_bounds__((1 << LOG2) / 16) void k_rows(RowArgs a, TwTables tw) {
-  constexpr int N2 = 1 << LOG2, T = N2 / 16, K = RP<LOG2>::K;
+// writes hash bits directly.  The last forward round and the first inverse
+// round act on the same 16 contiguous positions per group, so the seed
+// product happens in registers between them.
+template <int LOG2, int NX, int GPT, bool IN_BITS, bool SEED, bool OUT_BITS>
+__global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, TwTables tw) {
+  constexpr int N2 = 1 << LOG2, T = row_threads<LOG2, GPT>(), K = RP<LOG2>::K;
   static_assert(K >= 2, "rows are at least 2^5 long");
   static_assert(Geo<LOG2, K - 1>::r == 16 && Geo<LOG2, K - 1>::s == 1, "last round");
   __shared__ uint32_t lds[N2 + N2 / 16];
@@ -302,99 +352,125 @@ __global__ __launch_bounds__((1 << LOG2) / 16) void k_rows(RowArgs a, TwTables t
   const int lane = tid & 63;
   const int row = blockIdx.x;
   const int zy = blockIdx.y;
-  const int64_t Nc = (int64_t)1 << a.log_nc;
+  const int32_t Nc = 1 << a.log_nc;
 
-  auto ld_lds = [&](int i) -> uint32_t { return lds[i + (i >> 4)]; };
-  auto st_lds = [&](int i, uint32_t v) { lds[i + (i >> 4)] = v; };
+  auto ld_lds_k = [&](auto kc) {
+    return [&](int g, int e) -> uint32_t {
+      using G = Geo<LOG2, decltype(kc)::value>;
+      const int p0 = G::pos0(g);
+      return lds[p0 + (p0 >> 4) + e * G::SP];
+    };
+  };
+  auto st_lds_k = [&](auto kc) {
+    return [&](int g, int e, uint32_t v) {
+      using G = Geo<LOG2, decltype(kc)::value>;
+      const int p0 = G::pos0(g);
+      lds[p0 + (p0 >> 4) + e * G::SP] = v;
+    };
+  };
+  using G0 = Geo<LOG2, 0>;
+  constexpr std::integral_constant<int, 0> k0{};
 
-  uint32_t xs[NX][16];
+  uint32_t xs[NX][GPT][16];
   static_for<0, NX>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     const int item = SEED ? zy : zy * NX + c;
     if constexpr (IN_BITS) {
       const BitMap mp = a.map[SEED ? zy : c];
-      const uint64_t zo = SEED ? 0 : (uint64_t)zy * a.zs;
-      auto ld0 = [&](int q) -> uint32_t { return map_bit(a.bits, mp, q, Nc, zo); };
-      for (int g = tid; g < Geo<LOG2, 0>::groups; g += T)
-        fwd_group<LOG2, 0>(g, tw.fwd, ld0, st_lds);
+      const uint32_t* __restrict__ bits = a.bits + (SEED ? 0 : (uint64_t)zy * (a.zs >> 5));
+      auto ld0 = [&](int g, int e) -> uint32_t {
+        return map_bit(bits, mp, G0::pos0(g) + e * G0::s, Nc);
+      };
+      round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
     } else {
-      const uint32_t* __restrict__ src = a.in + (uint64_t)item * Nc + (uint64_t)row * N2;
-      auto ld0 = [&](int i) -> uint32_t { return src[i]; };
-      for (int g = tid; g < Geo<LOG2, 0>::groups; g += T)
-        fwd_group<LOG2, 0>(g, tw.fwd, ld0, st_lds);
+      const uint32_t* __restrict__ src = a.in + (uint64_t)item * (uint32_t)Nc + (uint64_t)row * N2;
+      auto ld0 = [&](int g, int e) -> uint32_t { return src[G0::pos0(g) + e * G0::s]; };
+      round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
     }
     __syncthreads();
     static_for<1, K - 1>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      for (int g = tid; g < Geo<LOG2, k>::groups; g += T)
-        fwd_group<LOG2, k>(g, tw.fwd, ld_lds, st_lds);
+      round_all<LOG2, decltype(kc)::value, T, GPT, false>(tid, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
       __syncthreads();
     });
 #pragma unroll
-    for (int e = 0; e < 16; ++e) xs[c][e] = ld_lds(tid * 16 + e);
-    dft_reg<16, false>(xs[c]);
+    for (int u = 0; u < GPT; ++u) {
+      const int g = tid + u * T;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xs[c][u][e] = lds[g * 17 + e];
+    }
+#pragma unroll
+    for (int u = 0; u < GPT; ++u) dft_reg<16, false>(xs[c][u]);
     __syncthreads();
   });
 
   if constexpr (SEED) {
-    uint32_t* dst = a.out + (uint64_t)zy * Nc + (uint64_t)row * N2 + tid * 16;
 #pragma unroll
-    for (int e = 0; e < 16; e += 4) {
-      uint4 w;
-      w.x = red1(mul_mont(xs[0][e + 0], a.cw));
-      w.y = red1(mul_mont(xs[0][e + 1], a.cw));
-      w.z = red1(mul_mont(xs[0][e + 2], a.cw));
-      w.w = red1(mul_mont(xs[0][e + 3], a.cw));
-      *reinterpret_cast<uint4*>(dst + e) = w;
+    for (int u = 0; u < GPT; ++u) {
+      uint32_t* dst = a.out + (uint64_t)zy * (uint32_t)Nc + (uint64_t)row * N2 + (tid + u * T) * 16;
+#pragma unroll
+      for (int e = 0; e < 16; e += 4) {
+        uint4 w;
+        w.x = red1(mul_mont(xs[0][u][e + 0], a.cw));
+        w.y = red1(mul_mont(xs[0][u][e + 1], a.cw));
+        w.z = red1(mul_mont(xs[0][u][e + 2], a.cw));
+        w.w = red1(mul_mont(xs[0][u][e + 3], a.cw));
+        *reinterpret_cast<uint4*>(dst + e) = w;
+      }
     }
     return;
   } else {
     for (int o = 0; o < a.ny; ++o) {
-      uint32_t acc[16];
+      uint32_t acc[GPT][16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = 0;
+      for (int u = 0; u < GPT; ++u)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[u][e] = 0;
       static_for<0, NX>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        const uint32_t* wr =
-            a.W + (uint64_t)(o - c + NX - 1) * Nc + (uint64_t)row * N2 + tid * 16;
+        const uint32_t* wr = a.W + (uint64_t)(o - c + NX - 1) * (uint32_t)Nc + (uint64_t)row * N2;
 #pragma unroll
-        for (int e = 0; e < 16; e += 4) {
-          uint4 w = *reinterpret_cast<const uint4*>(wr + e);
-          acc[e + 0] = red2(acc[e + 0] + mul_mont(xs[c][e + 0], w.x));
-          acc[e + 1] = red2(acc[e + 1] + mul_mont(xs[c][e + 1], w.y));
-          acc[e + 2] = red2(acc[e + 2] + mul_mont(xs[c][e + 2], w.z));
-          acc[e + 3] = red2(acc[e + 3] + mul_mont(xs[c][e + 3], w.w));
+        for (int u = 0; u < GPT; ++u) {
+          const uint32_t* wg = wr + (tid + u * T) * 16;
+#pragma unroll
+          for (int e = 0; e < 16; e += 4) {
+            const uint4 w = *reinterpret_cast<const uint4*>(wg + e);
+            acc[u][e + 0] = red2(acc[u][e + 0] + mul_mont(xs[c][u][e + 0], w.x));
+            acc[u][e + 1] = red2(acc[u][e + 1] + mul_mont(xs[c][u][e + 1], w.y));
+            acc[u][e + 2] = red2(acc[u][e + 2] + mul_mont(xs[c][u][e + 2], w.z));
+            acc[u][e + 3] = red2(acc[u][e + 3] + mul_mont(xs[c][u][e + 3], w.w));
+          }
         }
       });
-      dft_reg<16, true>(acc);
 #pragma unroll
-      for (int e = 0; e < 16; ++e) st_lds(tid * 16 + e, acc[e]);
+      for (int u = 0; u < GPT; ++u) {
+        dft_reg<16, true>(acc[u]);
+        const int g = tid + u * T;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lds[g * 17 + e] = acc[u][e];
+      }
       __syncthreads();
       static_for_down<1, K - 1>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        for (int g = tid; g < Geo<LOG2, k>::groups; g += T)
-          inv_group<LOG2, k>(g, tw.inv, ld_lds, st_lds);
+        round_all<LOG2, decltype(kc)::value, T, GPT, true>(tid, tw.inv, ld_lds_k(kc), st_lds_k(kc));
         __syncthreads();
       });
       if constexpr (OUT_BITS) {
         // the row is the whole transform: position q is output bit q
-        const uint64_t ybase = (uint64_t)zy * a.y_zs;
-        const int64_t yvalid = (int64_t)a.m;
-        const int64_t ylimit = (yvalid + 63) & ~(int64_t)63;
-        uint64_t* y64 = reinterpret_cast<uint64_t*>(a.y);
-        auto st_bits = [&](int q, uint32_t v) {
+        const int32_t yvalid = (int32_t)a.m;
+        const int32_t ylimit = (yvalid + 63) & ~63;
+        uint64_t* __restrict__ y64 = reinterpret_cast<uint64_t*>(a.y) + (uint64_t)zy * (a.y_zs >> 6);
+        auto st_bits = [&](int g, int e, uint32_t v) {
+          const int q = G0::pos0(g) + e * G0::s;
           const uint32_t bit = (q < yvalid) ? (red1(v) & 1u) : 0u;
           const uint64_t bal = __ballot(bit);
-          const int64_t q0 = q - lane;
-          if (lane == 0 && q0 < ylimit) y64[(ybase + (uint64_t)q0) >> 6] = bal;
+          const int q0 = q - lane;
+          if (lane == 0 && q0 < ylimit) y64[q0 >> 6] = bal;
         };
-        for (int g = tid; g < Geo<LOG2, 0>::groups; g += T)
-          inv_group<LOG2, 0>(g, tw.inv, ld_lds, st_bits);
+        round_all<LOG2, 0, T, GPT, true>(tid, tw.inv, ld_lds_k(k0), st_bits);
       } else {
-        uint32_t* dst = a.out + (uint64_t)(zy * a.ny + o) * Nc + (uint64_t)row * N2;
-        auto st0 = [&](int i, uint32_t v) { dst[i] = v; };
-        for (int g = tid; g < Geo<LOG2, 0>::groups; g += T)
-          inv_group<LOG2, 0>(g, tw.inv, ld_lds, st0);
+        uint32_t* __restrict__ dst =
+            a.out + (uint64_t)(zy * a.ny + o) * (uint32_t)Nc + (uint64_t)row * N2;
+        auto st0 = [&](int g, int e, uint32_t v) { dst[G0::pos0(g) + e * G0::s] = v; };
+        round_all<LOG2, 0, T, GPT, true>(tid, tw.inv, ld_lds_k(k0), st0);
       }
       __syncthreads();
     }
@@ -405,14 +481,14 @@ __global__ __launch_bounds__((1 << LOG2) / 16) void k_rows(RowArgs a, TwTables t
 template <int LOG1>
 hipError_t launch_cols_fwd(const ColFwdArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
   prof_begin(KID_COLS_FWD, s);
-  hipLaunchKernelGGL(k_cols_fwd<LOG1>, grid, dim3(256), 0, s, a, tw);
+  hipLaunchKernelGGL(k_cols_fwd<LOG1>, grid, dim3(COLS * CSLOTS), 0, s, a, tw);
   prof_end(KID_COLS_FWD, s);
   return hipGetLastError();
 }
 template <int LOG1>
 hipError_t launch_cols_inv(const ColInvArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
   prof_begin(KID_COLS_INV, s);
-  hipLaunchKernelGGL(k_cols_inv<LOG1>, grid, dim3(256), 0, s, a, tw);
+  hipLaunchKernelGGL(k_cols_inv<LOG1>, grid, dim3(COLS * CSLOTS), 0, s, a, tw);
   prof_end(KID_COLS_INV, s);
   return hipGetLastError();
 }
@@ -448,13 +524,20 @@ hipError_t cols_inv(int log1, const ColInvArgs& a, dim3 grid, const TwTables& tw
   return hipErrorInvalidValue;
 }
 
+// groups of the last round per thread: 2 where a row has >= 128 groups
+template <int LOG2>
+constexpr int row_gpt() {
+  return LOG2 >= 11 ? 2 : 1;
+}
+
 template <int LOG2, int NX, bool IN_BITS, bool SEED, bool OUT_BITS>
 hipError_t launch_rows(const RowArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
   constexpr int kid = IN_BITS ? (SEED ? KID_FUSED_SEED : KID_FUSED_HASH)
                               : (SEED ? KID_ROWS_SEED : KID_ROWS_HASH);
+  constexpr int G = row_gpt<LOG2>();
   prof_begin(kid, s);
-  hipLaunchKernelGGL((k_rows<LOG2, NX, IN_BITS, SEED, OUT_BITS>), grid, dim3((1 << LOG2) / 16),
-                     0, s, a, tw);
+  hipLaunchKernelGGL((k_rows<LOG2, NX, G, IN_BITS, SEED, OUT_BITS>), grid,
+                     dim3(row_threads<LOG2, G>()), 0, s, a, tw);
   prof_end(kid, s);
   return hipGetLastError();
 }
@@ -575,7 +658,7 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
   BitMap maps[MAXMAP];
   for (int w = 0; w < p.nwin; ++w) {
     const int64_t d = w - (p.nx - 1);
-    maps[w] = BitMap{(int64_t)n - 1 + d * p.by, 0, (int64_t)L, p.by};
+    maps[w] = BitMap{(int32_t)((int64_t)n - 1 + d * p.by), 0, (int32_t)L, (int32_t)p.by};
   }
   const uint32_t cw = (uint32_t)((uint64_t)host_pow(Nc % P, P - 2) * host_mont(host_mont(1)) % P);
   RowArgs r{};
@@ -620,7 +703,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   if (p.log1 == 0) {
     r.bits = x_bits;
     r.zs = x_stride_bits;
-    r.map[0] = BitMap{0, 0, (int64_t)n, Nc};
+    r.map[0] = BitMap{0, 0, (int32_t)n, (int32_t)Nc};
     return rows_l<1, true, false, true>(p.log2, r, dim3(1, batch), tw, s);
   }
   uint32_t* X = work;
@@ -631,7 +714,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   for (int k = 0; k < p.nx; ++k) {
     const int64_t lo = (int64_t)k * p.bx;
     const int64_t hi = lo + p.bx < (int64_t)n ? lo + p.bx : (int64_t)n;
-    c.map[k] = BitMap{lo, lo, hi, Nc};
+    c.map[k] = BitMap{(int32_t)lo, (int32_t)lo, (int32_t)hi, (int32_t)Nc};
   }
   c.nmap = p.nx;
   c.log2 = p.log2;
