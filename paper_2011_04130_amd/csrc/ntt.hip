@@ -95,6 +95,19 @@ __device__ __forceinline__ void static_for_down(F&& f) {
   }
 }
 
+// The r twiddles of one group as 16-byte loads (tables are 16-byte aligned:
+// every table offset and group stride is an even number of entries).
+template <int R>
+__device__ __forceinline__ void load_tw(const uint2* __restrict__ T, uint2 (&t)[R]) {
+  const uint4* T4 = reinterpret_cast<const uint4*>(T);
+#pragma unroll
+  for (int i = 0; i < R / 2; ++i) {
+    const uint4 q = T4[i];
+    t[2 * i] = make_uint2(q.x, q.y);
+    t[2 * i + 1] = make_uint2(q.z, q.w);
+  }
+}
+
 // One round on GPT groups g0 + u*gstep.  All loads are issued before any
 // butterfly and all stores after, so the groups' arithmetic interleaves and
 // hides load latency.  Forward: radix-r DIF then twiddle w_R^(b bitrev(a'));
@@ -113,23 +126,19 @@ __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __re
   for (int u = 0; u < GPT; ++u) {
     if constexpr (INV) {
       if constexpr (G::s > 1) {
-        const uint2* T = tws + G::toff + ((g0 + u * gstep) % G::s) * G::r;
+        uint2 t[G::r];
+        load_tw<G::r>(tws + G::toff + ((g0 + u * gstep) % G::s) * G::r, t);
 #pragma unroll
-        for (int a = 1; a < G::r; ++a) {
-          const uint2 t = T[a];
-          v[u][a] = mul_shoup(v[u][a], t.x, t.y);
-        }
+        for (int a = 1; a < G::r; ++a) v[u][a] = mul_shoup(v[u][a], t[a].x, t[a].y);
       }
       dft_reg<G::r, true>(v[u]);
     } else {
       dft_reg<G::r, false>(v[u]);
       if constexpr (G::s > 1) {
-        const uint2* T = tws + G::toff + ((g0 + u * gstep) % G::s) * G::r;
+        uint2 t[G::r];
+        load_tw<G::r>(tws + G::toff + ((g0 + u * gstep) % G::s) * G::r, t);
 #pragma unroll
-        for (int a = 1; a < G::r; ++a) {
-          const uint2 t = T[a];
-          v[u][a] = mul_shoup(v[u][a], t.x, t.y);
-        }
+        for (int a = 1; a < G::r; ++a) v[u][a] = mul_shoup(v[u][a], t[a].x, t[a].y);
       }
     }
   }
@@ -162,7 +171,10 @@ __device__ __forceinline__ uint32_t gtw(const TwTables& tw, uint32_t e) {
 
 template <int LOG>
 __device__ __forceinline__ int brev(int p) {
-  return (int)(__builtin_bitreverse32((uint32_t)p) >> (32 - LOG));
+  if constexpr (LOG == 0)
+    return 0;
+  else
+    return (int)(__builtin_bitreverse32((uint32_t)p) >> (32 - LOG));
 }
 
 // Transform position q of an item maps to bit off + (q < h ? q : q - Nc) of
@@ -178,6 +190,37 @@ __device__ __forceinline__ uint32_t map_bit(const uint32_t* __restrict__ bits, c
   const int32_t idx = mp.off + (q < mp.h ? q : q - Nc);
   if ((uint32_t)(idx - mp.lo) >= (uint32_t)(mp.hi - mp.lo)) return 0u;
   return (bits[(uint32_t)idx >> 5] >> (idx & 31)) & 1u;
+}
+
+// The 32 values of positions q0..q0+31 as one word (bit i = position q0+i).
+// Fast path: no wrap point and no range edge inside, so the word is a
+// funnel shift of two consecutive source words; otherwise bit by bit.
+__device__ __forceinline__ uint32_t stage_word(const uint32_t* __restrict__ bits,
+                                               const BitMap& mp, int32_t q0, int32_t Nc) {
+  const int32_t q1 = q0 + 31;
+  if (q1 < mp.h || q0 >= mp.h) {
+    const int32_t i0 = mp.off + (q0 < mp.h ? q0 : q0 - Nc);
+    if (i0 >= mp.lo && i0 + 31 < mp.hi) {
+      const uint32_t w = (uint32_t)i0 >> 5, sh = (uint32_t)i0 & 31u;
+      uint32_t v = bits[w] >> sh;
+      if (sh) v |= bits[w + 1] << (32u - sh);
+      return v;
+    }
+  }
+  uint32_t v = 0;
+  for (int i = 0; i < 32; ++i) v |= map_bit(bits, mp, q0 + i, Nc) << i;
+  return v;
+}
+
+// Montgomery-form powers u^0..u^(R-1) of u = w^e (u^0 = 2^32 mod p).
+template <int R>
+__device__ __forceinline__ void mont_powers(const TwTables& tw, uint32_t e, uint32_t (&up)[R]) {
+  up[0] = MONT_R;
+  if constexpr (R > 1) {
+    up[1] = gtw(tw, e);
+#pragma unroll
+    for (int t = 2; t < R; ++t) up[t] = mul_mont(up[t - 1], up[1]);
+  }
 }
 
 // ----------------------------------------------------------------- pass A
@@ -197,6 +240,7 @@ constexpr int CGMAX = 2;    // groups in flight per thread
 template <int LOG1>
 __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTables tw) {
   __shared__ uint32_t lds[(1 << LOG1) * COLS];
+  __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int32_t Nc = 1 << a.log_nc;
   const int j2 = blockIdx.x * COLS + c;
@@ -207,9 +251,12 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   const int l2 = a.log2;
 
+  for (int j1 = threadIdx.x; j1 < (1 << LOG1); j1 += COLS * CSLOTS)
+    wbits[j1] = stage_word(bits, mp, (j1 << l2) + (int)blockIdx.x * COLS, Nc);
+  __syncthreads();
   auto ld_bits = [&](int g, int e) -> uint32_t {
     const int j1 = Geo<LOG1, 0>::pos0(g) + e * Geo<LOG1, 0>::s;
-    return map_bit(bits, mp, (j1 << l2) + j2, Nc);
+    return (wbits[j1] >> c) & 1u;
   };
   auto ld_lds_k = [&](auto kc) {
     return [&](int g, int e) -> uint32_t {
@@ -224,10 +271,19 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
     };
   };
   constexpr int K = RP<LOG1>::K;
+  // four-step twiddle w_Nc^(j2 k1) of last-round position p = g*r + e:
+  // k1 = bitrev(p) = bitrev(e) 2^(LOG1-lgr) + bitrev(g), so the twiddle is
+  // B_g U^bitrev(e) with U = w_Nc^(j2 2^(LOG1-lgr)) fixed per thread
+  using GL = Geo<LOG1, K - 1>;
+  static_assert(GL::s == 1, "last round works on contiguous groups");
+  uint32_t upow[GL::r];
+  mont_powers<GL::r>(tw, (gstep << (LOG1 - GL::lgr)) & ((1u << LOG_MAX) - 1), upow);
+  uint32_t bg = 0;
   auto st_out = [&](int g, int e, uint32_t v) {
-    const int p = Geo<LOG1, K - 1>::pos0(g) + e * Geo<LOG1, K - 1>::s;
-    const uint32_t ex = gstep * (uint32_t)brev<LOG1>(p);
-    out[((uint32_t)p << l2) + j2] = mul_mont(v, gtw(tw, ex));
+    const int p = g * GL::r + e;
+    if (e == 0) bg = gtw(tw, gstep * (uint32_t)brev<LOG1 - GL::lgr>(g));
+    const uint32_t t = e ? mul_mont(bg, upow[brev<GL::lgr>(e)]) : bg;
+    out[((uint32_t)p << l2) + j2] = mul_mont(v, t);
   };
   static_for<0, K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -272,10 +328,17 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTable
   const int l2 = a.log2;
   constexpr int K = RP<LOG1>::K;
 
+  // inverse four-step twiddle, factored as in pass A
+  using GL = Geo<LOG1, K - 1>;
+  static_assert(GL::s == 1, "last round works on contiguous groups");
+  uint32_t upow[GL::r];
+  mont_powers<GL::r>(tw, (0u - (gstep << (LOG1 - GL::lgr))) & EMASK, upow);
+  uint32_t bg = 0;
   auto ld_in = [&](int g, int e) -> uint32_t {
-    const int p = Geo<LOG1, K - 1>::pos0(g) + e * Geo<LOG1, K - 1>::s;
-    const uint32_t ex = (0u - gstep * (uint32_t)brev<LOG1>(p)) & EMASK;
-    return mul_mont(in[((uint32_t)p << l2) + j2], gtw(tw, ex));
+    const int p = g * GL::r + e;
+    if (e == 0) bg = gtw(tw, (0u - gstep * (uint32_t)brev<LOG1 - GL::lgr>(g)) & EMASK);
+    const uint32_t t = e ? mul_mont(bg, upow[brev<GL::lgr>(e)]) : bg;
+    return mul_mont(in[((uint32_t)p << l2) + j2], t);
   };
   auto ld_lds_k = [&](auto kc) {
     return [&](int g, int e) -> uint32_t {
@@ -376,10 +439,15 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
     constexpr int c = decltype(cc)::value;
     const int item = SEED ? zy : zy * NX + c;
     if constexpr (IN_BITS) {
+      // the whole transform's input bits, 32 positions per LDS word
+      __shared__ uint32_t wbits[N2 / 32];
       const BitMap mp = a.map[SEED ? zy : c];
       const uint32_t* __restrict__ bits = a.bits + (SEED ? 0 : (uint64_t)zy * (a.zs >> 5));
+      for (int w = tid; w < N2 / 32; w += T) wbits[w] = stage_word(bits, mp, w * 32, Nc);
+      __syncthreads();
       auto ld0 = [&](int g, int e) -> uint32_t {
-        return map_bit(bits, mp, G0::pos0(g) + e * G0::s, Nc);
+        const int q = G0::pos0(g) + e * G0::s;
+        return (wbits[q >> 5] >> (q & 31)) & 1u;
       };
       round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
     } else {

@@ -14,7 +14,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/qrng.h"
+#include "qrng.h"
 #include "internal.h"
 
 using namespace qrng;
