@@ -150,6 +150,23 @@ qrng_status qrng_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_dev, uint
                                       uint32_t seed_id, uint64_t m, uint64_t *y_dev,
                                       int path, void *stream);
 
+/* One asynchronous pass of the whole path over a block of S 8-bit samples
+ * (S a multiple of 8): the histogram and the min-entropy estimate of Sec. II,
+ * the output length m of Sec. III.B (whole bits per sample, minus
+ * ceil(2 log2_inv_eps), clamped to [0, m_cap]) and the Toeplitz hash of the
+ * n = 8 S raw bits (the sample bytes themselves) with the first n+m-1 bits of
+ * registered seed `seed_id` -- all on the device, without synchronising the
+ * stream or copying anything to the host.  The transform is planned for
+ * m_cap, so y_dev holds ceil(m_cap/64) words; bits from m to m_cap are 0.
+ * m_dev / out_dev (nullable, device memory) receive m and the estimate
+ * (qrng_me_result) when the stream reaches them.  The seed must have at
+ * least n + m_cap - 1 bits.  Same estimate and bits as qrng_minentropy +
+ * qrng_output_bits + qrng_toeplitz_hash_seeded. */
+qrng_status qrng_extract(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
+                         const qrng_me_opts *opts, double log2_inv_eps, uint32_t seed_id,
+                         uint64_t m_cap, uint64_t *y_dev, uint64_t *m_dev,
+                         qrng_me_result *out_dev, int path, void *stream);
+
 /* Hash many blocks (Sec. III.E: a long raw sequence split into blocks) in one
  * enqueued batch.  `blocks_host` lists nblocks descriptors (host memory);
  * x_pool_dev / y_pool_dev are the raw and output pools the offsets refer to.

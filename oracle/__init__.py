@@ -250,6 +250,7 @@ def modified_toeplitz(r_bits: np.ndarray, a_bits: np.ndarray, m: int) -> np.ndar
 U_MODEL_ARGMAX = 0   # U = {argmax P}
 U_BOTH_ARGMAX = 1    # U = {argmax P, argmax P'}
 U_ALL = 2            # U = every sample value (total-variation distance)
+TIE_REL = 1e-9       # model probabilities this close (relative) are a tie
 
 
 def _phi(z: float) -> float:
@@ -286,13 +287,17 @@ def minentropy_dists(P: np.ndarray, Pa: np.ndarray, N: int,
     Delta H_m = log2(d_U / 2^-(N+1) + 1) with N the ADC bits per sample;
     H_modify = H_min - Delta H_m.  U is the argmax of P by default (the
     chain of inequalities replaces sum_U P by 2^-H_min), ties to the lowest
-    value.
+    value (ties within TIE_REL relative).
     """
     P = np.asarray(P, dtype=np.float64)
     Pa = np.asarray(Pa, dtype=np.float64)
-    um = int(np.argmax(P))          # first maximum: lowest value on ties
-    ua = int(np.argmax(Pa))
-    h_min = -math.log2(float(P[um]))
+    pmax = float(P.max())
+    # lowest value whose model probability equals the maximum; values within
+    # TIE_REL of it count as equal (a model centred half way between two codes
+    # gives two exactly equal bins, which rounding must not separate)
+    um = int(np.flatnonzero(P >= pmax * (1.0 - TIE_REL))[0])
+    ua = int(np.argmax(Pa))         # first maximum: lowest value on ties
+    h_min = -math.log2(pmax)
     h_act = -math.log2(float(Pa[ua])) if Pa[ua] > 0 else float("inf")
     if u_mode == U_MODEL_ARGMAX:
         U = [um]

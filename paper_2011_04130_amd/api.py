@@ -154,6 +154,35 @@ class Context:
                                                   _stream(torch, self.device, stream)))
         return y
 
+    def extract(self, samples, seed_id: int, m_cap: int, y=None, m_out=None, me_out=None,
+                model: int = MODEL_FIT, mu: float = 0.0, sigma: float = 0.0,
+                u_mode: int = U_MODEL_ARGMAX, log2_inv_eps: float = 0.0,
+                path: int = PATH_AUTO, stream=None):
+        """Asynchronous min-entropy -> m -> hash of 8-bit samples, all on the device.
+
+        m_out: int64 tensor of >= 1 element (receives m); me_out: uint8 tensor
+        of >= sizeof(qrng_me_result) bytes (receives the estimate).  Returns y.
+        """
+        torch = self._torch
+        sp = self._dev_tensor(samples, "samples", torch.uint8)
+        y = self._out(y, m_cap)
+        yp = self._dev_tensor(y, "y")
+        mp = self._dev_tensor(m_out, "m_out") if m_out is not None else None
+        if me_out is not None and me_out.numel() * me_out.element_size() < ctypes.sizeof(MeResult):
+            raise ValueError("me_out too small")
+        rp = self._dev_tensor(me_out, "me_out") if me_out is not None else None
+        opts = MeOpts(8, model, mu, sigma, u_mode, 0)
+        check(self._lib.qrng_extract(self._h, sp, samples.numel(), ctypes.byref(opts),
+                                     log2_inv_eps, seed_id, m_cap, yp, mp, rp, path,
+                                     _stream(torch, self.device, stream)))
+        return y
+
+    @staticmethod
+    def me_result_from_bytes(buf) -> dict:
+        """Decode a qrng_me_result read back from device memory (uint8 tensor)."""
+        raw = bytes(buf.cpu().numpy().tobytes()[: ctypes.sizeof(MeResult)])
+        return MeResult.from_buffer_copy(raw).as_dict()
+
     # -- Sec. III.E ---------------------------------------------------------
     def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
         """blocks: iterable of (x_word_off, n, m, y_word_off, seed_id)."""

@@ -61,8 +61,9 @@ __global__ __launch_bounds__(64) void k_direct(const uint32_t* __restrict__ S, u
                                                const uint32_t* __restrict__ Xr_all, uint64_t W,
                                                uint64_t m, uint64_t uchunk,
                                                uint32_t* __restrict__ y_all, uint64_t y_zs32,
-                                               uint32_t nrb) {
+                                               uint32_t nrb, const uint64_t* __restrict__ m_dev) {
   const uint64_t z = blockIdx.x / nrb;
+  if (m_dev && *m_dev < m) m = *m_dev;  // valid rows computed on the device
   const uint64_t G = (m + 31) / 32;
   const uint64_t grp = (uint64_t)(blockIdx.x % nrb) * 64 + threadIdx.x;
   const uint32_t* __restrict__ Xr = Xr_all + z * W;
@@ -117,7 +118,7 @@ uint64_t direct_work_words(uint64_t n, int batch) { return (uint64_t)batch * ((n
 hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits,
                        uint64_t m, uint32_t* y_bits, uint32_t* work, int num_cus,
                        hipStream_t s, int batch, uint64_t x_stride_bits,
-                       uint64_t y_stride_bits) {
+                       uint64_t y_stride_bits, const uint64_t* m_dev) {
   const uint64_t W = (n + 31) / 32;
   const uint64_t L = n + m - 1;
   const uint64_t nsw = (L + 31) / 32;  // seed words holding bits < L
@@ -143,7 +144,7 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
   nchunk = (W + 1 + uchunk - 1) / uchunk;
   prof_begin(KID_DIRECT, s);
   hipLaunchKernelGGL(k_direct, dim3(nrb * (uint32_t)batch, (uint32_t)nchunk), dim3(64), 0, s,
-                     seed_bits, nsw, work, W, m, uchunk, y_bits, y_stride_bits / 32, nrb);
+                     seed_bits, nsw, work, W, m, uchunk, y_bits, y_stride_bits / 32, nrb, m_dev);
   prof_end(KID_DIRECT, s);
   return hipGetLastError();
 }

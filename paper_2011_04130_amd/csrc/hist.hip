@@ -3,8 +3,11 @@
 // Each wave counts into its own LDS sub-histogram (fewer same-address
 // collisions), the workgroup merges them and adds to 64-bit global counters.
 // Values >= nbins are counted in an extra bin so the host can reject them.
+#include <math.h>
+
 #include "common.h"
 #include "internal.h"
+#include "qrng.h"
 
 namespace qrng {
 
@@ -60,7 +63,137 @@ __global__ void k_clear64(unsigned long long* p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
+// Block-wide reductions over the 256 threads of k_me_finish.
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+// index of the largest value, lowest index on ties
+__device__ int block_argmax(double v, int idx, double* sh, int* shi) {
+  sh[threadIdx.x] = v;
+  shi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double a = sh[threadIdx.x], b = sh[threadIdx.x + o];
+      const int ia = shi[threadIdx.x], ib = shi[threadIdx.x + o];
+      if (b > a || (b == a && ib < ia)) {
+        sh[threadIdx.x] = b;
+        shi[threadIdx.x] = ib;
+      }
+    }
+    __syncthreads();
+  }
+  const int r = shi[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ int block_min_index(int v, int* shi) {
+  shi[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) shi[threadIdx.x] = min(shi[threadIdx.x], shi[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const int r = shi[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double phi_dev(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+// Sec. II on the device, thread v owning sample value v: the same estimate
+// as the host finish of qrng_minentropy, then the output length (Sec. III.B).
+__global__ __launch_bounds__(256) void k_me_finish(MeDevArgs a) {
+  __shared__ double sh[256];
+  __shared__ int shi[256];
+  const int K = 1 << a.N;
+  const int v = threadIdx.x;
+  const double cv = v < K ? (double)a.counts[v] : 0.0;
+  const double S = block_sum(cv, sh);
+  double mu, sigma;
+  if (a.model == QRNG_MODEL_GIVEN) {
+    mu = a.mu;
+    sigma = a.sigma;
+  } else {
+    mu = block_sum((double)v * cv, sh) / S;
+    sigma = sqrt(block_sum(((double)v - mu) * ((double)v - mu) * cv, sh) / S);
+  }
+  double P = 0.0;
+  if (v < K) {
+    if (sigma > 0.0) {
+      const double lo = v == 0 ? 0.0 : phi_dev(((double)v - 0.5 - mu) / sigma);
+      const double hi = v == K - 1 ? 1.0 : phi_dev(((double)v + 0.5 - mu) / sigma);
+      P = hi - lo;
+    } else {
+      double at = floor(mu + 0.5);
+      at = at < 0.0 ? 0.0 : (at > K - 1 ? K - 1 : at);
+      P = (v == (int)at) ? 1.0 : 0.0;
+    }
+  }
+  // model argmax: lowest value within 1e-9 (relative) of max P, as on the host
+  const double pmax = block_max(v < K ? P : -1.0, sh);
+  const int um = block_min_index(v < K && P >= pmax * (1.0 - 1e-9) ? v : 1 << 30, shi);
+  const int ua = block_argmax(v < K ? cv : -1.0, v, sh, shi);
+  bool inU;
+  if (a.u_mode == QRNG_U_MODEL_ARGMAX)
+    inU = v == um;
+  else if (a.u_mode == QRNG_U_BOTH_ARGMAX)
+    inU = v == um || v == ua;
+  else
+    inU = v < K;
+  const double d = 0.5 * block_sum(inU ? fabs(cv / S - P) : 0.0, sh);
+  if (v == 0) {
+    qrng_me_result r;
+    r.mu_hat = mu;
+    r.sigma_hat = sigma;
+    r.h_min = -log2(pmax);
+    const double ca = (double)a.counts[ua];
+    r.h_actual = ca > 0 ? -log2(ca / S) : INFINITY;
+    r.d_u = d;
+    r.delta_h_m = log2(d * ldexp(1.0, a.N + 1) + 1.0);
+    r.h_mod = r.h_min - r.delta_h_m;
+    r.argmax_model = (uint32_t)um;
+    r.argmax_empirical = (uint32_t)ua;
+    r.samples = (uint64_t)S;
+    if (a.out) *reinterpret_cast<qrng_me_result*>(a.out) = r;
+    double h = floor(r.h_mod);
+    if (!(h > 0)) h = 0;
+    if (h > a.N) h = a.N;
+    const uint64_t base = (uint64_t)((unsigned __int128)a.n * (uint64_t)h / (uint64_t)a.N);
+    const double secd = ceil(2.0 * a.log2_inv_eps);
+    const uint64_t sec = secd >= 1.8e19 ? ~0ull : (uint64_t)secd;
+    uint64_t m = base > sec ? base - sec : 0;
+    if (m > a.m_cap) m = a.m_cap;
+    *a.m_out = m;
+  }
+}
+
 }  // namespace
+
+hipError_t minentropy_device(const MeDevArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_me_finish, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
                         unsigned long long* counts, int num_cus, hipStream_t s) {

@@ -59,10 +59,12 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
                             const TwTables& tw, hipStream_t s);
 // Hash `batch` equal blocks: block z reads raw bits from x_bits + z*x_stride_bits
 // and writes y_bits + z*y_stride_bits (both strides multiples of 64).
+// m_dev (nullable): the valid output length computed on the device (<= m,
+// which sizes the plan); output bits from it up to m are written as 0.
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
                     uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
-                    hipStream_t s);
+                    hipStream_t s, const uint64_t* m_dev = nullptr);
 
 // ------------------------------------------------------------- direct path
 // `batch` blocks sharing one seed: block z reads x_bits + z*x_stride_bits and
@@ -71,11 +73,26 @@ uint64_t direct_work_words(uint64_t n, int batch);
 hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits,
                        uint64_t m, uint32_t* y_bits, uint32_t* work, int num_cus,
                        hipStream_t s, int batch, uint64_t x_stride_bits,
-                       uint64_t y_stride_bits);
+                       uint64_t y_stride_bits, const uint64_t* m_dev = nullptr);
 
 // ------------------------------------------------------------- histogram
 hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
                         unsigned long long* counts /* nbins + 1 */, int num_cus,
                         hipStream_t s);
+
+// Min-entropy finish on the device (one workgroup): model, H_min, d_U,
+// Delta H_m, H_modify from the counts, and m = n H/N - 2 log2(1/eps)
+// (whole bits per sample, clamped to [0, m_cap]).  `out` is a qrng_me_result.
+struct MeDevArgs {
+  const unsigned long long* counts;
+  int N, model, u_mode;
+  double mu, sigma;
+  uint64_t n;
+  double log2_inv_eps;
+  uint64_t m_cap;
+  void* out;
+  uint64_t* m_out;
+};
+hipError_t minentropy_device(const MeDevArgs& a, hipStream_t s);
 
 }  // namespace qrng

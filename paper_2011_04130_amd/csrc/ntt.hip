@@ -306,8 +306,16 @@ struct ColInvArgs {
   uint32_t* y;    // output bits
   uint64_t y_zs;  // batch stride of the output (bits, multiple of 64)
   int64_t by;     // output chunk length
-  uint64_t m;
+  uint64_t m;     // output bits the plan covers (words up to m are written)
+  const uint64_t* m_dev;  // nullable: the valid output length, read on the device (<= m)
 };
+
+// valid output bits: the plan's m, or the smaller length computed on the device
+__device__ __forceinline__ uint64_t valid_bits(uint64_t m, const uint64_t* m_dev) {
+  if (!m_dev) return m;
+  const uint64_t d = *m_dev;
+  return d < m ? d : m;
+}
 
 template <int LOG1>
 __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTables tw) {
@@ -318,9 +326,10 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTable
   const int j2 = blockIdx.x * COLS + c;
   const int o = blockIdx.y % a.ny;
   const uint64_t ybase = (uint64_t)(blockIdx.y / a.ny) * a.y_zs + (uint64_t)o * a.by;
-  const int64_t rem = (int64_t)a.m - (int64_t)o * a.by;
-  const int32_t yvalid = (int32_t)(rem < a.by ? rem : a.by);
-  const int32_t ylimit = (yvalid + 63) & ~63;
+  const int64_t rem_cap = (int64_t)a.m - (int64_t)o * a.by;
+  const int32_t ylimit = ((int32_t)(rem_cap < a.by ? rem_cap : a.by) + 63) & ~63;
+  const int64_t rem = (int64_t)valid_bits(a.m, a.m_dev) - (int64_t)o * a.by;
+  const int32_t yvalid = (int32_t)(rem < a.by ? (rem < 0 ? 0 : rem) : a.by);
   uint32_t* __restrict__ ywords = a.y + (ybase >> 5);
   const uint32_t* __restrict__ in = a.in + (uint64_t)blockIdx.y * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
@@ -389,6 +398,7 @@ struct RowArgs {
   uint32_t* y;    // output bits (fused)
   uint64_t y_zs;
   uint64_t m;
+  const uint64_t* m_dev;  // nullable, as in ColInvArgs
 };
 
 // Threads of a row kernel: every thread owns GPT groups of the last round.
@@ -523,8 +533,8 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
       });
       if constexpr (OUT_BITS) {
         // the row is the whole transform: position q is output bit q
-        const int32_t yvalid = (int32_t)a.m;
-        const int32_t ylimit = (yvalid + 63) & ~63;
+        const int32_t yvalid = (int32_t)valid_bits(a.m, a.m_dev);
+        const int32_t ylimit = ((int32_t)a.m + 63) & ~63;
         uint64_t* __restrict__ y64 = reinterpret_cast<uint64_t*>(a.y) + (uint64_t)zy * (a.y_zs >> 6);
         auto st_bits = [&](int g, int e, uint32_t v) {
           const int q = G0::pos0(g) + e * G0::s;
@@ -758,7 +768,7 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
                     uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
-                    hipStream_t s) {
+                    hipStream_t s, const uint64_t* m_dev) {
   const int64_t Nc = (int64_t)1 << p.log_nc;
   RowArgs r{};
   r.W = W;
@@ -768,6 +778,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   r.y = y_bits;
   r.y_zs = y_stride_bits;
   r.m = m;
+  r.m_dev = m_dev;
   if (p.log1 == 0) {
     r.bits = x_bits;
     r.zs = x_stride_bits;
@@ -810,6 +821,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   ci.y_zs = y_stride_bits;
   ci.by = p.by;
   ci.m = m;
+  ci.m_dev = m_dev;
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, batch * p.ny), tw, s);
 }
 

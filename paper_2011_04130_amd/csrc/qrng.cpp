@@ -103,6 +103,8 @@ struct qrng_ctx {
   uint64_t work_words = 0;
   unsigned long long* counts_dev = nullptr;
   unsigned long long* counts_host = nullptr;  // pinned
+  qrng_me_result* me_dev = nullptr;           // qrng_extract's default result slot
+  uint64_t* m_dev = nullptr;                  // and output-length slot
   std::map<uint32_t, Seed> seeds;
   uint32_t next_seed = 1;
 };
@@ -184,19 +186,19 @@ int choose_path(uint64_t n, uint64_t m) {
 
 qrng_status run_direct(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                        uint64_t m, uint64_t* y, hipStream_t s, int batch, uint64_t xs,
-                       uint64_t ys) {
+                       uint64_t ys, const uint64_t* m_dev) {
   qrng_status st = ensure_work(ctx, direct_work_words(n, batch));
   if (st) return st;
   HIP_TRY(direct_hash(reinterpret_cast<const uint32_t*>(x), n,
                       reinterpret_cast<const uint32_t*>(seed), m, reinterpret_cast<uint32_t*>(y),
-                      ctx->work, ctx->num_cus, s, batch, xs, ys));
+                      ctx->work, ctx->num_cus, s, batch, xs, ys, m_dev));
   return QRNG_OK;
 }
 
 // NTT hash; W == nullptr computes the seed windows into the workspace first.
 qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                     const uint32_t* W, uint64_t m, uint64_t* y, hipStream_t s, int batch,
-                    uint64_t xs, uint64_t ys) {
+                    uint64_t xs, uint64_t ys, const uint64_t* m_dev) {
   NttPlan p;
   if (!ntt_make_plan(n, m, &p))
     return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
@@ -212,7 +214,7 @@ qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t
     W = Wt;
   }
   HIP_TRY(ntt_hash(p, reinterpret_cast<const uint32_t*>(x), n, m, W,
-                   reinterpret_cast<uint32_t*>(y), ctx->work, batch, xs, ys, ctx->tw, s));
+                   reinterpret_cast<uint32_t*>(y), ctx->work, batch, xs, ys, ctx->tw, s, m_dev));
   return QRNG_OK;
 }
 
@@ -249,23 +251,26 @@ qrng_status seed_spectra(qrng_ctx* ctx, Seed& sd, uint64_t n, uint64_t m, hipStr
   return QRNG_OK;
 }
 
+// m_dev (nullable): valid output length computed on the device, <= m.
 qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                      Seed* sd, uint64_t m, uint64_t* y, int path, hipStream_t s, int batch,
-                     uint64_t xs, uint64_t ys) {
+                     uint64_t xs, uint64_t ys, const uint64_t* m_dev = nullptr) {
   if (path == QRNG_PATH_AUTO) path = choose_path(n, m);
-  if (path == QRNG_PATH_DIRECT) return run_direct(ctx, x, n, seed, m, y, s, batch, xs, ys);
+  if (path == QRNG_PATH_DIRECT) return run_direct(ctx, x, n, seed, m, y, s, batch, xs, ys, m_dev);
   if (path == QRNG_PATH_NTT) {
     const uint32_t* W = nullptr;
     if (sd) {
       qrng_status st = seed_spectra(ctx, *sd, n, m, s, &W);
       if (st) return st;
     }
-    return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys);
+    return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys, m_dev);
   }
   return fail(QRNG_EUNSUPPORTED, "path %d is not available for this call", path);
 }
 
 double phi(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
+
+constexpr double kTieRel = 1e-9;  // relative closeness treated as a tie of model bins
 
 // Sec. II on the host: model P, H_min, d_U, Delta H_m, H_modify.
 void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o,
@@ -296,11 +301,17 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
     const double at = std::min<double>(std::max<double>(std::floor(mu + 0.5), 0.0), K - 1);
     for (int v = 0; v < K; ++v) P[v] = (v == (int)at) ? 1.0 : 0.0;
   }
-  int um = 0, ua = 0;
+  // model argmax: lowest value whose P is within kTieRel of the maximum (a
+  // model centred between two codes has two equal bins; rounding must not
+  // decide between them); observed argmax: lowest value on exact ties
+  double pmax = P[0];
+  int ua = 0;
   for (int v = 1; v < K; ++v) {
-    if (P[v] > P[um]) um = v;
+    pmax = std::max(pmax, P[v]);
     if (c[v] > c[ua]) ua = v;
   }
+  int um = 0;
+  while (P[um] < pmax * (1.0 - kTieRel)) ++um;
   std::vector<int> U;
   if (o.u_mode == QRNG_U_MODEL_ARGMAX) {
     U.push_back(um);
@@ -315,7 +326,7 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
   d *= 0.5;
   r->mu_hat = mu;
   r->sigma_hat = sigma;
-  r->h_min = -std::log2(P[um]);
+  r->h_min = -std::log2(pmax);
   r->h_actual = c[ua] ? -std::log2((double)c[ua] / S) : INFINITY;
   r->d_u = d;
   r->delta_h_m = std::log2(d * std::ldexp(1.0, N + 1) + 1.0);
@@ -419,6 +430,8 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
             hipMalloc(&c->g_lo, 4096 * 4) == hipSuccess &&
             hipMalloc(&c->g_hi, 2048 * 4) == hipSuccess &&
             hipMalloc(&c->counts_dev, 257 * 8) == hipSuccess &&
+            hipMalloc(&c->me_dev, sizeof(qrng_me_result)) == hipSuccess &&
+            hipMalloc(&c->m_dev, 8) == hipSuccess &&
             hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMemcpy(c->tw_fwd, f.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(c->tw_inv, iv.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
@@ -447,6 +460,8 @@ void qrng_destroy(qrng_ctx* c) {
   if (c->g_hi) (void)hipFree(c->g_hi);
   if (c->work) (void)hipFree(c->work);
   if (c->counts_dev) (void)hipFree(c->counts_dev);
+  if (c->me_dev) (void)hipFree(c->me_dev);
+  if (c->m_dev) (void)hipFree(c->m_dev);
   if (c->counts_host) (void)hipHostFree(c->counts_host);
   delete c;
 }
@@ -547,6 +562,59 @@ qrng_status qrng_toeplitz_hash_seeded(qrng_ctx* ctx, const uint64_t* x, uint64_t
   CtxScope cs(ctx);
   return hash_one(ctx, x, n, sd.ptr, &sd, m, y, path, reinterpret_cast<hipStream_t>(stream), 1,
                   0, 0);
+}
+
+qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
+                         const qrng_me_opts* opts, double log2_inv_eps, uint32_t seed_id,
+                         uint64_t m_cap, uint64_t* y, uint64_t* m_dev, qrng_me_result* out_dev,
+                         int path, void* stream) {
+  if (!ctx || !samples || !opts || !y) return fail(QRNG_EINVAL, "null argument");
+  if (opts->sample_bits != 8) return fail(QRNG_EINVAL, "qrng_extract hashes 8-bit samples");
+  if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
+    return fail(QRNG_EINVAL, "unknown model");
+  if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
+    return fail(QRNG_EINVAL, "unknown U mode");
+  if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
+  if (opts->model == QRNG_MODEL_GIVEN &&
+      !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
+    return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  if (std::isnan(log2_inv_eps) || log2_inv_eps < 0)
+    return fail(QRNG_EINVAL, "bad security parameter");
+  if (S == 0 || (S & 7)) return fail(QRNG_EINVAL, "S must be a positive multiple of 8");
+  if (!aligned8(samples) || !aligned8(y) || (m_dev && !aligned8(m_dev)) ||
+      (out_dev && !aligned8(out_dev)))
+    return fail(QRNG_EINVAL, "buffers must be 8-byte aligned");
+  auto it = ctx->seeds.find(seed_id);
+  if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  Seed& sd = it->second;
+  const uint64_t n = 8 * S;
+  if (m_cap == 0 || m_cap > n) return fail(QRNG_EINVAL, "m_cap must be in [1, n]");
+  if (n + m_cap - 1 > sd.L)
+    return fail(QRNG_EINVAL, "seed has %llu bits, the plan needs %llu", (unsigned long long)sd.L,
+                (unsigned long long)(n + m_cap - 1));
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  if (overlap(y, words64(m_cap) * 8, samples, S))
+    return fail(QRNG_EINVAL, "output overlaps the samples");
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint64_t* md = m_dev ? m_dev : ctx->m_dev;
+  HIP_TRY(histogram_u8(samples, S, 256, ctx->counts_dev, ctx->num_cus, s));
+  MeDevArgs a{};
+  a.counts = ctx->counts_dev;
+  a.N = 8;
+  a.model = opts->model;
+  a.u_mode = opts->u_mode;
+  a.mu = opts->mu;
+  a.sigma = opts->sigma;
+  a.n = n;
+  a.log2_inv_eps = log2_inv_eps;
+  a.m_cap = m_cap;
+  a.out = out_dev ? (void*)out_dev : (void*)ctx->me_dev;
+  a.m_out = md;
+  HIP_TRY(minentropy_device(a, s));
+  return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y, path,
+                  s, 1, 0, 0, md);
 }
 
 qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,

@@ -250,3 +250,66 @@ def test_seeded_and_batched_equal_single(torch, ctx):
                 assert np.array_equal(single, want)
     finally:
         ctx.unregister_seed(sid)
+
+
+# ------------------------------------------------ one asynchronous pass
+
+@pytest.mark.parametrize("cfg_k,path,cap_frac", [(0, 1, 1.0), (0, 2, 1.0), (0, 2, 0.5),
+                                                  (1, 2, 1.0), (1, 1, 0.75)])
+def test_extract_matches_oracle(torch, ctx, cfg_k, path, cap_frac):
+    """Device min-entropy, device m and the hash in one call equal the oracle."""
+    c = qi.config(cfg_k)
+    log("extract %s path=%d cap=%.2f" % (c["name"], path, cap_frac))
+    s = qi.gen_adc(c["S"], c["sigma"], seed=c["adc_seed"])
+    n = 8 * c["S"]
+    m_cap = int(n * cap_frac)
+    ref = oracle.minentropy_counts(oracle.histogram(s, 8), 8)
+    m = min(oracle.output_bits(n, 8, ref["h_mod"]), m_cap)
+    sw = qi.gen_seed_words(n + m_cap - 1, c["seed_seed"])
+    st = dev(torch, sw)
+    sid = ctx.register_seed(st, n + m_cap - 1)
+    try:
+        m_out = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        me_out = torch.zeros(128, dtype=torch.uint8, device="cuda:0")
+        y = torch.full(((m_cap + 63) // 64,), -1, dtype=torch.int64, device="cuda:0")
+        ctx.extract(torch.from_numpy(s).to("cuda:0"), sid, m_cap, y=y, m_out=m_out,
+                    me_out=me_out, path=path)
+        torch.cuda.synchronize()
+        me = ctx.me_result_from_bytes(me_out)
+        for k in ("mu_hat", "sigma_hat", "h_min", "h_actual", "d_u", "delta_h_m", "h_mod"):
+            assert abs(me[k] - ref[k]) <= TOL, (k, me[k], ref[k])
+        assert int(m_out.item()) == m
+        xw = qi.samples_as_words(s)
+        want = ref_hash(xw, n, sw, m)
+        got = host(y)
+        nw = (m + 63) // 64
+        assert np.array_equal(got[:nw], want)
+        assert not got[nw:].any()          # bits m..m_cap are written as zero
+    finally:
+        ctx.unregister_seed(sid)
+
+
+def test_extract_security_term_and_given_model(torch, ctx):
+    c = qi.config(0)
+    s = qi.gen_adc(c["S"], 12.0, seed=31)
+    n = 8 * c["S"]
+    sw = qi.gen_seed_words(2 * n, 32)
+    sid = ctx.register_seed(dev(torch, sw), 2 * n - 1)
+    try:
+        for (model, mu, sigma, u_mode, eps) in [(0, 0.0, 0.0, 1, 20.0), (1, 128.0, 11.0, 2, 0.0),
+                                                (1, 120.5, 12.5, 0, 3.5)]:
+            ref = oracle.minentropy_counts(oracle.histogram(s, 8), 8,
+                                           mu=mu if model else None,
+                                           sigma=sigma if model else None, u_mode=u_mode)
+            m = oracle.output_bits(n, 8, ref["h_mod"], eps)
+            m_out = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+            y = ctx.extract(torch.from_numpy(s).to("cuda:0"), sid, n, m_out=m_out, model=model,
+                            mu=mu, sigma=sigma, u_mode=u_mode, log2_inv_eps=eps, path=2)
+            torch.cuda.synchronize()
+            assert int(m_out.item()) == m
+            want = oracle.toeplitz_packed(qi.samples_as_words(s), n, sw, m)
+            got = host(y)
+            assert np.array_equal(got[: len(want)], want)
+            assert not got[len(want):].any()
+    finally:
+        ctx.unregister_seed(sid)

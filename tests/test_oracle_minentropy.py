@@ -157,3 +157,15 @@ def test_single_block_workload_gives_81920():
     assert math.floor(r["h_mod"]) == 5
     assert abs(r["h_mod"] - round(r["h_mod"])) > 1e-9
     assert oracle.output_bits(c["n"], 8, r["h_mod"]) == c["m_expected"] == 81920
+
+
+def test_tie_between_model_bins_takes_lowest_value():
+    # a model mean half way between two codes makes their probabilities equal;
+    # rounding must not pick between them: the lowest value is U
+    for mu in (120.5, 99.5, 200.5):
+        P = oracle.gaussian_model(8, mu, 12.5)
+        k = int(mu)
+        assert abs(P[k] - P[k + 1]) <= 1e-15
+        r = oracle.minentropy_dists(P, P, 8)
+        assert r["argmax_model"] == k
+        assert r["h_min"] == -math.log2(P.max())
