@@ -75,6 +75,13 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
                        hipStream_t s, int batch, uint64_t x_stride_bits,
                        uint64_t y_stride_bits, const uint64_t* m_dev = nullptr);
 
+// -------------------------------------------------------------- MFMA path
+// `batch` blocks sharing one seed as one int8 matrix product (strides as in
+// ntt_hash).  No workspace.
+hipError_t mfma_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits, uint64_t m,
+                     uint32_t* y_bits, int batch, uint64_t x_stride_bits,
+                     uint64_t y_stride_bits, hipStream_t s, const uint64_t* m_dev = nullptr);
+
 // ------------------------------------------------------------- histogram
 hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
                         unsigned long long* counts /* nbins + 1 */, int num_cus,

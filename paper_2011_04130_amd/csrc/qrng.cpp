@@ -265,6 +265,11 @@ qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_
     }
     return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys, m_dev);
   }
+  if (path == QRNG_PATH_MFMA) {
+    HIP_TRY(mfma_hash(reinterpret_cast<const uint32_t*>(x), n, reinterpret_cast<const uint32_t*>(seed),
+                      m, reinterpret_cast<uint32_t*>(y), batch, xs, ys, s, m_dev));
+    return QRNG_OK;
+  }
   return fail(QRNG_EUNSUPPORTED, "path %d is not available for this call", path);
 }
 

@@ -1,0 +1,92 @@
+"""GPU parity of the multi-block paths: the int8 matrix-core product over
+blocks sharing one seed, and batches of blocks against the oracle and
+against the single-block call (0 differing bits)."""
+import numpy as np
+import pytest
+
+import oracle
+import qrng_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2011_04130_amd as q
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, words):
+    return torch.from_numpy(np.ascontiguousarray(words).view(np.int64).copy()).to("cuda:0")
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def strided_blocks(nblk, n, m, sid, x_pad=0, y_pad=0, y0=0):
+    xw, yw = (n + 63) // 64 + x_pad, (m + 63) // 64 + y_pad
+    return [(b * xw, n, m, y0 + b * yw, sid) for b in range(nblk)], xw * nblk, y0 + yw * nblk
+
+
+@pytest.mark.parametrize("n,m,nblk", [(64, 40, 5), (4096, 2560, 300), (4000, 2500, 129),
+                                      (16384, 10240, 130), (1000, 1000, 7), (333, 1, 3),
+                                      (96, 32, 1)])
+@pytest.mark.parametrize("path", [1, 2, 3])
+def test_shared_seed_blocks_match_oracle(torch, ctx, n, m, nblk, path):
+    log("blocks n=%d m=%d B=%d path=%d" % (n, m, nblk, path))
+    sw = qi.gen_seed_words(n + m - 1, n + 17 * m)
+    sid = ctx.register_seed(dev(torch, sw), n + m - 1)
+    try:
+        blocks, xwords, ywords = strided_blocks(nblk, n, m, sid, y0=1)
+        xw = qi.gen_bits(64 * xwords, nblk + n)
+        yt = torch.full((ywords + 1,), -1, dtype=torch.int64, device="cuda:0")
+        ctx.hash_batched(blocks, dev(torch, xw), yt, path=path)
+        got = host(yt)
+        assert got[0] == np.uint64(2 ** 64 - 1)          # untouched before the pool
+        for (xo, bn, bm, yo, _) in blocks:
+            want = oracle.toeplitz_packed(xw[xo: xo + (bn + 63) // 64], bn, sw, bm)
+            assert np.array_equal(got[yo: yo + len(want)], want), (xo, yo)
+    finally:
+        ctx.unregister_seed(sid)
+
+
+def test_mfma_single_block_and_sweep_slice(torch, ctx):
+    # a slice of the block-length sweep: 2^12-bit blocks of Gaussian ADC data
+    c = qi.config(2)
+    n, m = 4096, 2560
+    nblk = 1024
+    s = qi.gen_adc(nblk * n // 8, c["sigma"], seed=c["adc_seed"])
+    xw = qi.samples_as_words(s)
+    sw = qi.gen_seed_words(n + m - 1, c["seed_seed"])
+    sid = ctx.register_seed(dev(torch, sw), n + m - 1)
+    try:
+        blocks, _, ywords = strided_blocks(nblk, n, m, sid)
+        xt = dev(torch, xw)
+        outs = {}
+        for path in (1, 2, 3):
+            yt = torch.zeros(ywords, dtype=torch.int64, device="cuda:0")
+            ctx.hash_batched(blocks, xt, yt, path=path)
+            outs[path] = host(yt)
+        assert np.array_equal(outs[1], outs[2]) and np.array_equal(outs[1], outs[3])
+        for b in (0, 1, 511, 1023):
+            want = oracle.toeplitz_packed(xw[b * 64:(b + 1) * 64], n, sw, m)
+            assert np.array_equal(outs[3][b * 40:(b + 1) * 40], want)
+        # the single-block call on the MFMA path (a batch of one)
+        y1 = host(ctx.hash_seeded(xt[64:128], n, sid, m, path=3))
+        assert np.array_equal(y1, outs[1][40:80])
+    finally:
+        ctx.unregister_seed(sid)
