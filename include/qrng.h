@@ -167,6 +167,17 @@ qrng_status qrng_extract(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
                          uint64_t m_cap, uint64_t *y_dev, uint64_t *m_dev,
                          qrng_me_result *out_dev, int path, void *stream);
 
+/* Sec. III.E (Fig. 5): a long raw sequence cut into nblocks equal blocks.
+ * Block b is the n bits starting at word b*x_stride_words of x_pool_dev; its
+ * m-bit hash with the first n+m-1 bits of registered seed `seed_id` goes to
+ * word b*y_stride_words of y_pool_dev.  Strides are at least ceil(n/64) and
+ * ceil(m/64); the pools must not overlap.  Each block's bits equal
+ * qrng_toeplitz_hash_seeded on that block alone.  Enqueued on `stream`. */
+qrng_status qrng_toeplitz_hash_strided(qrng_ctx *ctx, const uint64_t *x_pool_dev, uint64_t n,
+                                       uint64_t x_stride_words, uint32_t seed_id, uint64_t m,
+                                       uint64_t *y_pool_dev, uint64_t y_stride_words,
+                                       uint32_t nblocks, int path, void *stream);
+
 /* Hash many blocks (Sec. III.E: a long raw sequence split into blocks) in one
  * enqueued batch.  `blocks_host` lists nblocks descriptors (host memory);
  * x_pool_dev / y_pool_dev are the raw and output pools the offsets refer to.

@@ -51,7 +51,8 @@ _lib = None
 EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
-           "qrng_toeplitz_hash_batched", "qrng_extract", "qrng_profile_enable", "qrng_profile_kernel_name",
+           "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
+           "qrng_profile_enable", "qrng_profile_kernel_name",
            "qrng_profile_query", "qrng_profile_reset"]
 
 
@@ -88,6 +89,9 @@ def load_library(path: str | None = None):
     lib.qrng_toeplitz_hash_batched.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp,
                                                i32, vp]
     lib.qrng_toeplitz_hash_batched.restype = i32
+    lib.qrng_toeplitz_hash_strided.argtypes = [vp, vp, u64, u64, u32, u64, vp, u64, u32, i32,
+                                               vp]
+    lib.qrng_toeplitz_hash_strided.restype = i32
     lib.qrng_extract.argtypes = [vp, vp, u64, ctypes.POINTER(MeOpts), ctypes.c_double, u32,
                                  u64, vp, vp, vp, i32, vp]
     lib.qrng_extract.restype = i32

@@ -184,20 +184,43 @@ class Context:
         return MeResult.from_buffer_copy(raw).as_dict()
 
     # -- Sec. III.E ---------------------------------------------------------
-    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
-        """blocks: iterable of (x_word_off, n, m, y_word_off, seed_id)."""
+    def hash_strided(self, x_pool, n: int, x_stride_words: int, seed_id: int, m: int, y_pool,
+                     y_stride_words: int, nblocks: int, path: int = PATH_AUTO, stream=None):
+        """Equal blocks at constant strides (a long sequence cut into blocks)."""
         torch = self._torch
-        bl = list(blocks)
-        arr = (Block * max(len(bl), 1))()
-        xw = x_pool.numel() * x_pool.element_size() // 8
-        yw = y_pool.numel() * y_pool.element_size() // 8
-        for i, (xo, n, m, yo, sid) in enumerate(bl):
-            if xo + _words(n) > xw or yo + _words(m) > yw:
-                raise ValueError("block %d lies outside its pool" % i)
-            arr[i] = Block(xo, n, m, yo, sid, 0)
+        if nblocks and (x_pool.numel() * x_pool.element_size() // 8
+                        < (nblocks - 1) * x_stride_words + _words(n)):
+            raise ValueError("x_pool too small")
+        if nblocks and (y_pool.numel() * y_pool.element_size() // 8
+                        < (nblocks - 1) * y_stride_words + _words(m)):
+            raise ValueError("y_pool too small")
         xp = self._dev_tensor(x_pool, "x_pool")
         yp = self._dev_tensor(y_pool, "y_pool")
-        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(bl), xp, yp, path,
+        check(self._lib.qrng_toeplitz_hash_strided(self._h, xp, n, x_stride_words, seed_id, m, yp,
+                                                   y_stride_words, nblocks, path,
+                                                   _stream(torch, self.device, stream)))
+        return y_pool
+
+    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
+        """blocks: (k, 5) integer array or iterable of
+        (x_word_off, n, m, y_word_off, seed_id)."""
+        import numpy as np
+        torch = self._torch
+        a = np.asarray(blocks, dtype=np.uint64).reshape(-1, 5)
+        xw = x_pool.numel() * x_pool.element_size() // 8
+        yw = y_pool.numel() * y_pool.element_size() // 8
+        words = lambda b: (b + np.uint64(63)) // np.uint64(64)
+        bad = (a[:, 0] + words(a[:, 1]) > xw) | (a[:, 3] + words(a[:, 2]) > yw)
+        if bad.any():
+            raise ValueError("block %d lies outside its pool" % int(np.flatnonzero(bad)[0]))
+        rec = np.zeros(len(a), dtype=np.dtype([("x", "<u8"), ("n", "<u8"), ("m", "<u8"),
+                                               ("y", "<u8"), ("sid", "<u4"), ("flags", "<u4")]))
+        rec["x"], rec["n"], rec["m"], rec["y"], rec["sid"] = a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4]
+        assert rec.dtype.itemsize == ctypes.sizeof(Block)
+        arr = rec.ctypes.data_as(ctypes.POINTER(Block))
+        xp = self._dev_tensor(x_pool, "x_pool")
+        yp = self._dev_tensor(y_pool, "y_pool")
+        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(a), xp, yp, path,
                                                    _stream(torch, self.device, stream)))
         return y_pool
 

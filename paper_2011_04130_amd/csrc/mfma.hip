@@ -8,14 +8,14 @@
 // accumulation is exact and the hash bit is Y & 1.
 //
 // Tiling (gfx950, v_mfma_i32_32x32x32_i8, wave64): a workgroup owns 128
-// output rows x 128 blocks; wave w owns rows 32w..32w+31 and all 128 blocks
-// (four 32x32 accumulators).  Per K-chunk of 128 raw bits the workgroup
-// expands the 128 blocks' bits to bytes in LDS once (shared by the four
-// waves); each wave builds its A fragments in registers straight from the
-// seed bits (16 consecutive seed bits, reversed, expanded to 16 bytes), then
-// issues 4 MFMAs per 32-bit K-step.  Fragment layout: lane l holds row or
-// column l % 32 and 16 k-values of lane group l / 32 (the same k order on A
-// and B, so the contraction over k is exact whatever the hardware's order).
+// output rows x 256 blocks; each wave owns 64 blocks and all 128 rows
+// (eight 32x32 accumulators).  B fragments (raw bits) are built in registers
+// from the wave's own blocks; A fragments (the Toeplitz matrix) come from an
+// LDS tile of the reversed seed window expanded to bytes, shared by the four
+// waves.  Per 32-bit K-step a wave issues 8 MFMAs.  Fragment layout: lane l
+// holds row or column l % 32 and 16 k-values of lane group l / 32 (the same
+// k order on A and B, so the contraction over k is exact whatever the
+// hardware's order).
 #include "common.h"
 #include "internal.h"
 
@@ -26,10 +26,8 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int MT = 128;       // rows per workgroup
-constexpr int NT = 128;       // blocks per workgroup
-constexpr int KC = 128;       // raw bits per LDS fill
-constexpr int BROW = KC + 16; // padded LDS row (bytes) of one block's expanded bits
+constexpr int MT = 128;  // rows per workgroup
+constexpr int KC = 512;  // raw bits per K-chunk
 
 // 4 bits -> 4 bytes holding 0/1 (bit t to the low bit of byte t)
 __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
@@ -63,7 +61,7 @@ __device__ __forceinline__ uint32_t bits32_at(const uint32_t* __restrict__ s, in
 }
 
 struct MfmaArgs {
-  const uint32_t* x;  // raw bits; block b at bit b * x_zs
+  const uint32_t* x;  // raw bits; block b at bit b * x_zs (x_zs a multiple of 32)
   uint64_t x_zs;
   const uint32_t* seed;
   uint64_t n, m, L;
@@ -73,83 +71,140 @@ struct MfmaArgs {
   const uint64_t* m_dev;  // nullable: valid rows computed on the device
 };
 
-__global__ __launch_bounds__(256) void k_mfma(MfmaArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t bt[NT * BROW];
+constexpr int WNB = 2;             // 32-block tiles per wave
+constexpr int NTB = 4 * 32 * WNB;  // blocks per workgroup (4 waves)
+constexpr int KW = KC / 32;        // raw words per block per K-chunk
+constexpr int XROW = KW + 1;       // padded LDS row (words) of one block's chunk
+constexpr int RSPAN = MT + KC;     // bytes of one shifted copy of the seed window
+constexpr int RSTRIDE = RSPAN + 16;
+constexpr int SWORDS = (RSPAN + 64) / 32 + 2;  // seed words covering the window
+
+// Workgroup tile: MT = 128 rows x NTB = 256 blocks.  Wave w owns blocks
+// 64w..64w+63 and all four 32-row tiles (8 accumulators).  A[i][k] =
+// s[n-1+i-k]: for rows i0+ri and k = k0+kk the seed index is base - u with
+// u = (MT-1) - ri + kk and base = n-1+i0-k0+MT-1, so one K-chunk needs the
+// seed bits base-u, u < MT+KC, reversed ("rs[u]").  LDS holds 16 copies
+// rs[j + c] so that every A fragment (16 consecutive u) is one aligned
+// 16-byte read.  Raw bits are staged per K-chunk with 64-byte coalesced loads.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mfma(MfmaArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t rs[16 * RSTRIDE];
+  __shared__ uint32_t xs[NTB * XROW];
+  __shared__ uint32_t sw[SWORDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * MT + wave * 32;  // this wave's first row
-  const uint32_t b0 = blockIdx.y * NT;
-  const int64_t n = (int64_t)a.n;
+  const int64_t i0 = (int64_t)blockIdx.x * MT;
+  const int64_t n = (int64_t)a.n, L = (int64_t)a.L;
+  const uint32_t bg = blockIdx.y * NTB;  // workgroup's first block
   uint64_t mv = a.m;
   if (a.m_dev && *a.m_dev < mv) mv = *a.m_dev;
+  const int64_t nsw = (L + 31) >> 5;
 
-  v16i acc[4];
+  v16i acc[4][WNB];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[t][r] = 0;
-
-  // fill roles: thread -> (block bl, half hf of the K-chunk)
-  const int bl = tid >> 1, hf = tid & 1;
-  const uint32_t bfill = b0 + bl;
-  const int64_t arow = i0 + (lane & 31);  // A row of this lane
-  const int kg = 16 * (lane >> 5);        // lane group's k offset in a K-step
-
-  for (int64_t k0 = 0; k0 < n; k0 += KC) {
-    // expand 64 raw bits of block bfill (k0 + 64 hf ...) to bytes in LDS
-    {
-      uint32_t w0 = 0, w1 = 0;
-      if (bfill < a.nblocks) {
-        const int64_t base = (int64_t)bfill * (int64_t)a.x_zs;
-        const int64_t kk = k0 + 64 * hf;
-        w0 = bits32_at(a.x, base + kk, base + n);
-        w1 = bits32_at(a.x, base + kk + 32, base + n);
-      }
-      uint8_t* dst = bt + bl * BROW + 64 * hf;
+    for (int u = 0; u < WNB; ++u)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const uint32_t w = q ? w1 : w0;
-        v4i e0 = expand16(w & 0xFFFFu), e1 = expand16(w >> 16);
-        *reinterpret_cast<v4i*>(dst + 32 * q) = e0;
-        *reinterpret_cast<v4i*>(dst + 32 * q + 16) = e1;
+      for (int r = 0; r < 16; ++r) acc[t][u][r] = 0;
+
+  const int kg = 16 * (lane >> 5);  // lane group's k offset within a K-step
+  const int rl = lane & 31;
+
+  // Global reads of one K-chunk: the seed words of its window (threads
+  // below SWORDS) and NTB*KW raw words (XPT per thread, 64-byte runs per
+  // 16 lanes).  They are issued one chunk ahead, into registers.
+  constexpr int XPT = NTB * KW / 256;
+  static_assert(NTB * KW % 256 == 0, "raw words per thread");
+  uint32_t pre_x[XPT], pre_s = 0;
+  auto fetch = [&](int64_t k0) {
+    const int64_t base = n - 1 + i0 - k0 + (MT - 1);
+    const int64_t wlo = ((base - RSPAN - 32) >> 5);
+    if (tid < SWORDS) {
+      const int64_t w = wlo + tid;
+      uint32_t v = (w >= 0 && w < nsw) ? a.seed[w] : 0u;
+      const int64_t top = L - 32 * w;  // bits of word w below L
+      if (top < 32) v &= top <= 0 ? 0u : ((1u << (uint32_t)top) - 1u);
+      pre_s = v;
+    }
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int d = tid + 256 * e;
+      const int bl = d / KW, q = d % KW;
+      const uint32_t b = bg + bl;
+      const int64_t kb = k0 + 32 * q;
+      uint32_t v = 0;
+      if (b < a.nblocks && kb < n) {
+        v = a.x[((uint64_t)b * a.x_zs >> 5) + (kb >> 5)];
+        if (kb + 32 > n) v &= (1u << (uint32_t)(n - kb)) - 1u;
       }
+      pre_x[e] = v;
+    }
+  };
+  fetch(0);
+  for (int64_t k0 = 0; k0 < n; k0 += KC) {
+    const int64_t base = n - 1 + i0 - k0 + (MT - 1);
+    const int64_t wlo = ((base - RSPAN - 32) >> 5);
+    if (tid < SWORDS) sw[tid] = pre_s;
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int d = tid + 256 * e;
+      xs[(d / KW) * XROW + d % KW] = pre_x[e];
+    }
+    if (k0 + KC < n) fetch(k0 + KC);
+    __syncthreads();
+    // copy c, dword j: bytes rs[4j+c .. 4j+c+3] = seed bits base-(4j+c) down to base-(4j+c)-3
+    for (int d = tid; d < 16 * (RSTRIDE / 4); d += 256) {
+      const int c = d / (RSTRIDE / 4), j = d % (RSTRIDE / 4);
+      const int64_t p = base - (4 * j + c) - 3 - 32 * wlo;  // bit offset in sw
+      const int pw = (int)(p >> 5), ps = (int)(p & 31);
+      uint32_t w4 = sw[pw] >> ps;
+      if (ps > 28) w4 |= sw[pw + 1] << (32 - ps);
+      const uint32_t rev = (__builtin_bitreverse32(w4 & 15u) >> 28) & 15u;
+      *reinterpret_cast<uint32_t*>(rs + c * RSTRIDE + 4 * j) = expand4(rev);
     }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < KC / 32; ++ks) {
-      // A fragment: row arow, k = k0 + 32 ks + kg + q (q < 16) needs seed bit
-      // n-1+arow-k, i.e. the 16 bits ending at n-1+arow-(k0+32ks+kg), reversed
-      const int64_t phi = n - 1 + arow - (k0 + 32 * ks + kg);
-      const uint32_t w16 = bits32_at(a.seed, phi - 15, (int64_t)a.L) & 0xFFFFu;
-      const v4i af = expand16(__builtin_bitreverse32(w16) >> 16);
+    for (int ks = 0; ks < KW; ++ks) {
+      v4i bf[WNB];
+#pragma unroll
+      for (int u = 0; u < WNB; ++u) {
+        const int bl = wave * 32 * WNB + 32 * u + rl;
+        bf[u] = expand16((xs[bl * XROW + ks] >> kg) & 0xFFFFu);
+      }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const v4i bf =
-            *reinterpret_cast<const v4i*>(bt + (32 * t + (lane & 31)) * BROW + 32 * ks + kg);
-        acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf, acc[t], 0, 0, 0);
+        // rows ri = 32t + rl, k offset kk = 32 ks + kg: u0 = MT-1 - ri + kk
+        const int u0 = (MT - 1) - (32 * t + rl) + 32 * ks + kg;
+        const v4i af = *reinterpret_cast<const v4i*>(rs + (u0 & 15) * RSTRIDE + (u0 & ~15));
+#pragma unroll
+        for (int u = 0; u < WNB; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[u], acc[t][u], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
   // D layout: lane l holds column l % 32 (a block) and rows
-  // 8 (r / 4) + 4 (l / 32) + r % 4 of its accumulator, r < 16
+  // 8 (r / 4) + 4 (l / 32) + r % 4 of each accumulator, r < 16
+  const uint32_t bw = bg + wave * 32 * WNB;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    uint32_t w = 0;
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      w |= ((uint32_t)acc[t][r] & 1u) << row;
+    for (int u = 0; u < WNB; ++u) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        w |= ((uint32_t)acc[t][u][r] & 1u) << row;
+      }
+      w |= __shfl_xor(w, 32);
+      const uint32_t b = bw + 32 * u + rl;
+      const int64_t it = i0 + 32 * t;
+      if (lane < 32 && b < a.nblocks && it < (int64_t)a.m) {
+        const int64_t valid = (int64_t)mv - it;  // rows past the valid length are 0
+        if (valid < 32) w &= valid <= 0 ? 0u : ((1u << (uint32_t)valid) - 1u);
+        a.y[((uint64_t)b * a.y_zs + (uint64_t)it) >> 5] = w;
+      }
     }
-    w |= __shfl_xor(w, 32);
-    const uint32_t b = b0 + 32 * t + (lane & 31);
-    if (lane < 32 && b < a.nblocks && i0 < (int64_t)a.m) {
-      // rows past the valid length are 0
-      const int64_t valid = (int64_t)mv - i0;
-      if (valid < 32) w &= valid <= 0 ? 0u : ((1u << (uint32_t)valid) - 1u);
-      a.y[((uint64_t)b * a.y_zs + (uint64_t)i0) >> 5] = w;
-    }
-  }
 }
 
 // zero the 32-bit word after the last written one where ceil(m/32) is odd,
@@ -176,7 +231,7 @@ hipError_t mfma_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bi
   a.y_zs = y_stride_bits;
   a.nblocks = (uint32_t)batch;
   a.m_dev = m_dev;
-  const dim3 grid((unsigned)((m + MT - 1) / MT), (unsigned)((batch + NT - 1) / NT));
+  const dim3 grid((unsigned)((m + MT - 1) / MT), (unsigned)((batch + NTB - 1) / NTB));
   prof_begin(KID_MFMA, s);
   hipLaunchKernelGGL(k_mfma, grid, dim3(256), 0, s, a);
   if (((m + 31) / 32) & 1)

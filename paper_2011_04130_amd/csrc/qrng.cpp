@@ -622,6 +622,43 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
                   s, 1, 0, 0, md);
 }
 
+qrng_status qrng_toeplitz_hash_strided(qrng_ctx* ctx, const uint64_t* x_pool, uint64_t n,
+                                       uint64_t x_stride_words, uint32_t seed_id, uint64_t m,
+                                       uint64_t* y_pool, uint64_t y_stride_words,
+                                       uint32_t nblocks, int path, void* stream) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  auto it = ctx->seeds.find(seed_id);
+  if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  Seed& sd = it->second;
+  qrng_status st = check_hash_args(ctx, x_pool, n, sd.ptr, m, y_pool, path);
+  if (st || m == 0 || nblocks == 0) return st;
+  if (x_stride_words < words64(n) || y_stride_words < words64(m))
+    return fail(QRNG_EINVAL, "strides shorter than a block");
+  if (n + m - 1 > sd.L) return fail(QRNG_EINVAL, "seed too short for the block shape");
+  if (overlap(y_pool, (nblocks - 1) * y_stride_words * 8 + words64(m) * 8, x_pool,
+              (nblocks - 1) * x_stride_words * 8 + words64(n) * 8))
+    return fail(QRNG_EINVAL, "output pool overlaps the raw pool");
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int p = path == QRNG_PATH_AUTO ? choose_path(n, m) : path;
+  uint64_t cap = nblocks;
+  if (p == QRNG_PATH_NTT) {
+    NttPlan pl;
+    if (ntt_make_plan(n, m, &pl)) {
+      const uint64_t per = ntt_work_elems(pl, 1) * 4;
+      if (per) cap = std::max<uint64_t>(1, (1ull << 30) / per);  // 1 GiB of workspace
+    }
+  }
+  for (uint64_t b = 0; b < nblocks; b += cap) {
+    const uint64_t cnt = std::min<uint64_t>(cap, nblocks - b);
+    st = hash_one(ctx, x_pool + b * x_stride_words, n, sd.ptr, &sd, m, y_pool + b * y_stride_words,
+                  p, s, (int)cnt, x_stride_words * 64, y_stride_words * 64);
+    if (st) return st;
+  }
+  return QRNG_OK;
+}
+
 qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
                                        uint32_t nblocks, const uint64_t* x_pool,
                                        uint64_t* y_pool, int path, void* stream) {
