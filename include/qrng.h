@@ -188,6 +188,75 @@ qrng_status qrng_toeplitz_hash_batched(qrng_ctx *ctx, const qrng_block *blocks_h
                                        uint32_t nblocks, const uint64_t *x_pool_dev,
                                        uint64_t *y_pool_dev, int path, void *stream);
 
+/* ------------------------------------------------------------------ plans
+ * An uneven batch fixed once and replayed (Sec. III.E: a raw sequence cut
+ * into blocks, here of unequal lengths, each with the output length its own
+ * Sec. II estimate allows).  Creating a plan validates the descriptors,
+ * copies them to device memory, prepares the seed spectra, groups the blocks
+ * by transform length (blocks of one length share each launch) and,
+ * with QRNG_PLAN_GRAPH, records the launches as one HIP graph.  The pools and
+ * m_dev / me_dev are bound to the plan: every execution reads x_pool_dev as
+ * it is then and rewrites the outputs.
+ *
+ * QRNG_PLAN_ESTIMATE: block b's raw bits are its n/8 bytes of 8-bit samples
+ *   (n a multiple of 64); its histogram and Sec. II estimate run on the
+ *   device (opts, log2_inv_eps as in qrng_extract), m_dev[b] receives its
+ *   output length m_b = min(blocks[b].m, n H/8 - ceil(2 log2_inv_eps)) and
+ *   me_dev[b] (nullable) its estimate; blocks[b].m is the cap the output
+ *   is sized for (bits from m_b up to it are written as 0).
+ *   Without it each block's m is blocks[b].m and m_dev / me_dev are unused.
+ * QRNG_PLAN_TUNE: time the candidate launch shapes of every transform-length
+ *   class now (this runs the plan's kernels on `stream` and writes the
+ *   outputs), keep the fastest, and remember it in the context's tuning
+ *   table (qrng_tune_export / qrng_tune_import) for later plans.
+ * QRNG_PLAN_GRAPH: qrng_plan_execute replays one HIP graph.
+ *
+ * Seeds used by a live plan cannot be unregistered (QRNG_EBUSY).  Each
+ * block's result equals qrng_toeplitz_hash_seeded on that block alone (with
+ * m = m_dev[b] under QRNG_PLAN_ESTIMATE).  One plan must not be executed on
+ * two streams at once (its workspace is shared); qrng_destroy destroys the
+ * context's remaining plans. */
+enum {
+  QRNG_PLAN_ESTIMATE = 1,
+  QRNG_PLAN_GRAPH = 2,
+  QRNG_PLAN_TUNE = 4
+};
+
+typedef struct qrng_plan qrng_plan;
+
+typedef struct {
+  uint32_t blocks;          /* descriptors */
+  uint32_t classes;         /* transform-length classes launched together */
+  uint32_t launches;        /* launch groups per execution (estimate included) */
+  uint32_t graph;           /* 1 if executions replay a HIP graph */
+  uint64_t workspace_bytes; /* device workspace the plan owns */
+} qrng_plan_info;
+
+qrng_status qrng_plan_create(qrng_ctx *ctx, const qrng_block *blocks_host, uint32_t nblocks,
+                             const uint64_t *x_pool_dev, uint64_t *y_pool_dev,
+                             uint64_t *m_dev, qrng_me_result *me_dev,
+                             const qrng_me_opts *opts, double log2_inv_eps, int path,
+                             uint32_t flags, void *stream, qrng_plan **plan);
+
+/* Enqueue one execution of the plan on `stream`. */
+qrng_status qrng_plan_execute(qrng_plan *plan, void *stream);
+
+qrng_status qrng_plan_query(const qrng_plan *plan, qrng_plan_info *info);
+
+/* Waits for the device, then frees the plan.  NULL is a no-op. */
+void qrng_plan_destroy(qrng_plan *plan);
+
+/* The context's tuning table as text, one line per entry
+ * "ntt <log2 Nc> <ceil log2 class size> <shape>" (shape: log2 of the
+ * per-launch workspace cap in bytes, 40 = none, -1 = one direct launch per
+ * block).  *len receives the length without the terminating 0; buf
+ * (nullable) receives the text if cap > len. */
+qrng_status qrng_tune_export(qrng_ctx *ctx, char *buf, uint64_t cap, uint64_t *len);
+
+/* Merge a table written by qrng_tune_export (EINVAL on a malformed line,
+ * nothing merged then). */
+qrng_status qrng_tune_import(qrng_ctx *ctx, const char *text);
+
 /* Measurement aid.  While enabled, every kernel the context launches is
  * bracketed by HIP events recorded on the stream it runs on (a few
  * microseconds of host overhead per launch; results are unchanged). */

@@ -11,6 +11,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = 0, -1, -2, -3, -4, -5
 PATH_AUTO, PATH_DIRECT, PATH_NTT, PATH_MFMA = 0, 1, 2, 3
 U_MODEL_ARGMAX, U_BOTH_ARGMAX, U_ALL = 0, 1, 2
 MODEL_FIT, MODEL_GIVEN = 0, 1
+PLAN_ESTIMATE, PLAN_GRAPH, PLAN_TUNE = 1, 2, 4
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
           EUNSUPPORTED: "EUNSUPPORTED", EBUSY: "EBUSY"}
@@ -45,6 +46,15 @@ class Block(ctypes.Structure):
                 ("seed_id", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_uint32), ("classes", ctypes.c_uint32),
+                ("launches", ctypes.c_uint32), ("graph", ctypes.c_uint32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 # every symbol the header declares
@@ -52,6 +62,8 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
            "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
+           "qrng_plan_create", "qrng_plan_execute", "qrng_plan_query", "qrng_plan_destroy",
+           "qrng_tune_export", "qrng_tune_import",
            "qrng_profile_enable", "qrng_profile_kernel_name",
            "qrng_profile_query", "qrng_profile_reset"]
 
@@ -95,6 +107,20 @@ def load_library(path: str | None = None):
     lib.qrng_extract.argtypes = [vp, vp, u64, ctypes.POINTER(MeOpts), ctypes.c_double, u32,
                                  u64, vp, vp, vp, i32, vp]
     lib.qrng_extract.restype = i32
+    lib.qrng_plan_create.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp, vp, vp,
+                                     ctypes.POINTER(MeOpts), ctypes.c_double, i32, u32, vp,
+                                     ctypes.POINTER(vp)]
+    lib.qrng_plan_create.restype = i32
+    lib.qrng_plan_execute.argtypes = [vp, vp]
+    lib.qrng_plan_execute.restype = i32
+    lib.qrng_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.qrng_plan_query.restype = i32
+    lib.qrng_plan_destroy.argtypes = [vp]
+    lib.qrng_plan_destroy.restype = None
+    lib.qrng_tune_export.argtypes = [vp, ctypes.c_char_p, u64, ctypes.POINTER(u64)]
+    lib.qrng_tune_export.restype = i32
+    lib.qrng_tune_import.argtypes = [vp, ctypes.c_char_p]
+    lib.qrng_tune_import.restype = i32
     lib.qrng_profile_enable.argtypes = [vp, i32]
     lib.qrng_profile_enable.restype = i32
     lib.qrng_profile_kernel_name.argtypes = [i32]

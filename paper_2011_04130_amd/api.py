@@ -9,8 +9,9 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, U_MODEL_ARGMAX, Block, MeOpts, MeResult,
-                   QrngError, check, kernel_names, load_library)
+from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, PLAN_ESTIMATE, PLAN_GRAPH, PLAN_TUNE,
+                   U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, check,
+                   kernel_names, load_library)
 
 
 def _words(bits: int) -> int:
@@ -201,11 +202,10 @@ class Context:
                                                    _stream(torch, self.device, stream)))
         return y_pool
 
-    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
-        """blocks: (k, 5) integer array or iterable of
-        (x_word_off, n, m, y_word_off, seed_id)."""
+    @staticmethod
+    def _block_records(blocks, x_pool, y_pool):
+        """Checked qrng_block records (numpy) for (x_word_off, n, m, y_word_off, seed_id) rows."""
         import numpy as np
-        torch = self._torch
         a = np.asarray(blocks, dtype=np.uint64).reshape(-1, 5)
         xw = x_pool.numel() * x_pool.element_size() // 8
         yw = y_pool.numel() * y_pool.element_size() // 8
@@ -217,12 +217,107 @@ class Context:
                                                ("y", "<u8"), ("sid", "<u4"), ("flags", "<u4")]))
         rec["x"], rec["n"], rec["m"], rec["y"], rec["sid"] = a[:, 0], a[:, 1], a[:, 2], a[:, 3], a[:, 4]
         assert rec.dtype.itemsize == ctypes.sizeof(Block)
+        return rec
+
+    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
+        """blocks: (k, 5) integer array or iterable of
+        (x_word_off, n, m, y_word_off, seed_id)."""
+        torch = self._torch
+        rec = self._block_records(blocks, x_pool, y_pool)
         arr = rec.ctypes.data_as(ctypes.POINTER(Block))
         xp = self._dev_tensor(x_pool, "x_pool")
         yp = self._dev_tensor(y_pool, "y_pool")
-        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(a), xp, yp, path,
+        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(rec), xp, yp, path,
                                                    _stream(torch, self.device, stream)))
         return y_pool
 
+    # -- uneven batches fixed once ---------------------------------------------
+    def plan(self, blocks, x_pool, y_pool, m_out=None, me_out=None, estimate: bool = False,
+             graph: bool = False, tune: bool = False, model: int = MODEL_FIT, mu: float = 0.0,
+             sigma: float = 0.0, u_mode: int = U_MODEL_ARGMAX, log2_inv_eps: float = 0.0,
+             path: int = PATH_AUTO, stream=None) -> "Plan":
+        """A qrng_plan over (x_word_off, n, m, y_word_off, seed_id) rows.
 
-__all__ = ["Context", "QrngError"]
+        With estimate=True, m is each block's cap and m_out (int64 tensor of
+        len(blocks)) receives the output lengths; me_out (uint8 tensor of
+        len(blocks) * sizeof(qrng_me_result) bytes) the estimates.
+        """
+        torch = self._torch
+        rec = self._block_records(blocks, x_pool, y_pool)
+        k = len(rec)
+        xp = self._dev_tensor(x_pool, "x_pool")
+        yp = self._dev_tensor(y_pool, "y_pool")
+        mp = rp = None
+        if m_out is not None:
+            if m_out.numel() * m_out.element_size() < 8 * k:
+                raise ValueError("m_out holds fewer than len(blocks) lengths")
+            mp = self._dev_tensor(m_out, "m_out")
+        if me_out is not None:
+            if me_out.numel() * me_out.element_size() < k * ctypes.sizeof(MeResult):
+                raise ValueError("me_out too small")
+            rp = self._dev_tensor(me_out, "me_out")
+        flags = (PLAN_ESTIMATE if estimate else 0) | (PLAN_GRAPH if graph else 0) | \
+                (PLAN_TUNE if tune else 0)
+        opts = MeOpts(8, model, mu, sigma, u_mode, 0)
+        h = ctypes.c_void_p()
+        check(self._lib.qrng_plan_create(self._h, rec.ctypes.data_as(ctypes.POINTER(Block)), k,
+                                         xp, yp, mp, rp, ctypes.byref(opts), log2_inv_eps, path,
+                                         flags, _stream(torch, self.device, stream),
+                                         ctypes.byref(h)))
+        return Plan(self, h, (x_pool, y_pool, m_out, me_out))
+
+    def tune_export(self) -> str:
+        n = ctypes.c_uint64()
+        check(self._lib.qrng_tune_export(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value + 1)
+        check(self._lib.qrng_tune_export(self._h, buf, n.value + 1, ctypes.byref(n)))
+        return buf.value.decode()
+
+    def tune_import(self, text: str) -> None:
+        check(self._lib.qrng_tune_import(self._h, text.encode()))
+
+    def tune_save(self, path: str) -> None:
+        with open(path, "w") as f:
+            f.write(self.tune_export())
+
+    def tune_load(self, path: str) -> None:
+        with open(path) as f:
+            self.tune_import(f.read())
+
+
+class Plan:
+    """An uneven batch fixed once (see Context.plan); keeps its buffers alive."""
+
+    def __init__(self, ctx: Context, handle, keep):
+        self._ctx = ctx
+        self._h = handle
+        self._keep = keep
+
+    def execute(self, stream=None) -> None:
+        torch = self._ctx._torch
+        check(self._ctx._lib.qrng_plan_execute(self._h, _stream(torch, self._ctx.device, stream)))
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        check(self._ctx._lib.qrng_plan_query(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and getattr(self._ctx, "_h", None):
+            self._ctx._lib.qrng_plan_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Context", "Plan", "QrngError"]

@@ -65,6 +65,7 @@ __global__ void k_clear64(unsigned long long* p, int n) {
 
 // Block-wide reductions over the 256 threads of k_me_finish.
 __device__ double block_sum(double v, double* sh) {
+  __syncthreads();
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -121,19 +122,20 @@ __device__ int block_min_index(int v, int* shi) {
 
 __device__ double phi_dev(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
 
-// Sec. II on the device, thread v owning sample value v: the same estimate
-// as the host finish of qrng_minentropy, then the output length (Sec. III.B).
-__global__ __launch_bounds__(256) void k_me_finish(MeDevArgs a) {
-  __shared__ double sh[256];
-  __shared__ int shi[256];
-  const int K = 1 << a.N;
+// Sec. II on the device for one sample block, thread v (of 256) owning
+// sample value v with count cv: the same estimate as the host finish of
+// qrng_minentropy, then the output length of Sec. III.B.  sh: 257 doubles.
+__device__ void me_estimate(double cv, int N, int model, int u_mode, double mu_given,
+                            double sigma_given, uint64_t n, double log2_inv_eps, uint64_t m_cap,
+                            qrng_me_result* out, uint64_t* m_out, double* sh, int* shi) {
+  const int K = 1 << N;
   const int v = threadIdx.x;
-  const double cv = v < K ? (double)a.counts[v] : 0.0;
+  if (v >= K) cv = 0.0;
   const double S = block_sum(cv, sh);
   double mu, sigma;
-  if (a.model == QRNG_MODEL_GIVEN) {
-    mu = a.mu;
-    sigma = a.sigma;
+  if (model == QRNG_MODEL_GIVEN) {
+    mu = mu_given;
+    sigma = sigma_given;
   } else {
     mu = block_sum((double)v * cv, sh) / S;
     sigma = sqrt(block_sum(((double)v - mu) * ((double)v - mu) * cv, sh) / S);
@@ -155,43 +157,103 @@ __global__ __launch_bounds__(256) void k_me_finish(MeDevArgs a) {
   const int um = block_min_index(v < K && P >= pmax * (1.0 - 1e-9) ? v : 1 << 30, shi);
   const int ua = block_argmax(v < K ? cv : -1.0, v, sh, shi);
   bool inU;
-  if (a.u_mode == QRNG_U_MODEL_ARGMAX)
+  if (u_mode == QRNG_U_MODEL_ARGMAX)
     inU = v == um;
-  else if (a.u_mode == QRNG_U_BOTH_ARGMAX)
+  else if (u_mode == QRNG_U_BOTH_ARGMAX)
     inU = v == um || v == ua;
   else
     inU = v < K;
   const double d = 0.5 * block_sum(inU ? fabs(cv / S - P) : 0.0, sh);
+  if (v == ua) sh[256] = cv;
+  __syncthreads();
   if (v == 0) {
     qrng_me_result r;
     r.mu_hat = mu;
     r.sigma_hat = sigma;
     r.h_min = -log2(pmax);
-    const double ca = (double)a.counts[ua];
+    const double ca = sh[256];
     r.h_actual = ca > 0 ? -log2(ca / S) : INFINITY;
     r.d_u = d;
-    r.delta_h_m = log2(d * ldexp(1.0, a.N + 1) + 1.0);
+    r.delta_h_m = log2(d * ldexp(1.0, N + 1) + 1.0);
     r.h_mod = r.h_min - r.delta_h_m;
     r.argmax_model = (uint32_t)um;
     r.argmax_empirical = (uint32_t)ua;
     r.samples = (uint64_t)S;
-    if (a.out) *reinterpret_cast<qrng_me_result*>(a.out) = r;
+    if (out) *out = r;
     double h = floor(r.h_mod);
     if (!(h > 0)) h = 0;
-    if (h > a.N) h = a.N;
-    const uint64_t base = (uint64_t)((unsigned __int128)a.n * (uint64_t)h / (uint64_t)a.N);
-    const double secd = ceil(2.0 * a.log2_inv_eps);
+    if (h > N) h = N;
+    const uint64_t base = (uint64_t)((unsigned __int128)n * (uint64_t)h / (uint64_t)N);
+    const double secd = ceil(2.0 * log2_inv_eps);
     const uint64_t sec = secd >= 1.8e19 ? ~0ull : (uint64_t)secd;
     uint64_t m = base > sec ? base - sec : 0;
-    if (m > a.m_cap) m = a.m_cap;
-    *a.m_out = m;
+    if (m > m_cap) m = m_cap;
+    *m_out = m;
   }
+}
+
+__global__ __launch_bounds__(256) void k_me_finish(MeDevArgs a) {
+  __shared__ double sh[257];
+  __shared__ int shi[256];
+  const int v = threadIdx.x;
+  const double cv = v < (1 << a.N) ? (double)a.counts[v] : 0.0;
+  me_estimate(cv, a.N, a.model, a.u_mode, a.mu, a.sigma, a.n, a.log2_inv_eps, a.m_cap,
+              reinterpret_cast<qrng_me_result*>(a.out), a.m_out, sh, shi);
+}
+
+// One workgroup per block of an uneven batch: histogram of the block's
+// 8-bit samples in LDS (one sub-histogram per wave), then its estimate and
+// output length.  Sample bytes start 8-byte aligned; S is a multiple of 8.
+__global__ __launch_bounds__(256) void k_block_estimate(MeBatchArgs a) {
+  __shared__ uint32_t h[4][256];
+  __shared__ double sh[257];
+  __shared__ int shi[256];
+  const MeBlock blk = a.blocks[blockIdx.x];
+  const int v = threadIdx.x, wave = v >> 6;
+  for (int i = v; i < 4 * 256; i += 256) (&h[0][0])[i] = 0u;
+  __syncthreads();
+  uint32_t* hw = h[wave];
+  const uint2* s2 = reinterpret_cast<const uint2*>(a.pool + blk.byte_off);
+  const uint32_t nv = blk.S >> 3;
+  uint32_t i = v;
+  for (; i + 3 * 256 < nv; i += 4 * 256) {
+    uint2 w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = s2[i + k * 256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        atomicAdd(&hw[(w[k].x >> (8 * b)) & 255u], 1u);
+        atomicAdd(&hw[(w[k].y >> (8 * b)) & 255u], 1u);
+      }
+  }
+  for (; i < nv; i += 256) {
+    const uint2 w = s2[i];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      atomicAdd(&hw[(w.x >> (8 * b)) & 255u], 1u);
+      atomicAdd(&hw[(w.y >> (8 * b)) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  const double cv = (double)(h[0][v] + h[1][v] + h[2][v] + h[3][v]);
+  me_estimate(cv, 8, a.model, a.u_mode, a.mu, a.sigma, blk.n, a.log2_inv_eps, blk.m_cap,
+              a.out ? a.out + blockIdx.x : nullptr, a.m_out + blockIdx.x, sh, shi);
 }
 
 }  // namespace
 
 hipError_t minentropy_device(const MeDevArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_me_finish, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t minentropy_blocks(const MeBatchArgs& a, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  prof_begin(KID_HIST, s);
+  hipLaunchKernelGGL(k_block_estimate, dim3(nblocks), dim3(256), 0, s, a);
+  prof_end(KID_HIST, s);
   return hipGetLastError();
 }
 

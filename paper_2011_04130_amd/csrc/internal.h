@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qrng.h"
+
 namespace qrng {
 
 // ------------------------------------------------------- kernel timing hooks
@@ -49,18 +51,41 @@ struct NttPlan {
   int nwin;         // seed windows = nx + ny - 1
 };
 bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* plan);
+// The plan of one transform of length 2^log_nc (10 <= log_nc <= 23).
+bool ntt_plan_for_length(int log_nc, NttPlan* plan);
+
+// One block of an uneven batch whose blocks share a transform length
+// (n+m-1 <= Nc <= 2^23 for each).  Raw bits at x_pool + x_bit, output at
+// y_pool + y_bit (both multiples of 64), seed spectrum W (Nc words, from
+// ntt_seed_spectra with one transform, Nc and the block's seed).
+struct NttItem {
+  uint64_t x_bit, y_bit;
+  const uint32_t* W;
+  uint32_t n, m;  // m: output bits planned (words up to m are written)
+  uint32_t blk;   // index into the valid-length array m_arr
+  uint32_t pad;
+};
 // workspace (uint32 entries) for seed windows and for one hash of `batch` blocks
 uint64_t ntt_seed_elems(const NttPlan& p);
 uint64_t ntt_work_elems(const NttPlan& p, int batch);
 
 // Transform-domain seed: nwin arrays of Nc words (Montgomery form, 1/Nc folded).
+// With one transform (nx = ny = 1) the spectrum is that of the seed's first
+// Nc bits (seed_avail bits exist; the rest read as 0) and depends on the seed
+// and Nc only; above 2^23 it depends on (n, m).
 hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_t n,
-                            uint64_t m, uint32_t* W, uint32_t* work,
+                            uint64_t m, uint64_t seed_avail, uint32_t* W, uint32_t* work,
                             const TwTables& tw, hipStream_t s);
 // Hash `batch` equal blocks: block z reads raw bits from x_bits + z*x_stride_bits
 // and writes y_bits + z*y_stride_bits (both strides multiples of 64).
 // m_dev (nullable): the valid output length computed on the device (<= m,
 // which sizes the plan); output bits from it up to m are written as 0.
+// `count` uneven blocks of one transform length: items is device memory;
+// m_arr (nullable) holds valid output lengths (<= each item's m) by blk.
+// Workspace: ntt_work_elems(p, count).
+hipError_t ntt_hash_items(const NttPlan& p, const uint32_t* x_pool, const NttItem* items,
+                          int count, uint32_t* y_pool, const uint64_t* m_arr, uint32_t* work,
+                          const TwTables& tw, hipStream_t s);
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
                     uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
@@ -101,5 +126,26 @@ struct MeDevArgs {
   uint64_t* m_out;
 };
 hipError_t minentropy_device(const MeDevArgs& a, hipStream_t s);
+
+// Per-block estimates of an uneven batch of 8-bit sample blocks (one
+// workgroup each): block b's histogram, estimate (out[b], nullable) and
+// output length m_out[b] = min(m_cap, n H/8 - ceil(2 log2(1/eps))).
+struct MeBlock {
+  uint64_t byte_off;  // first sample (multiple of 8)
+  uint32_t S;         // samples (multiple of 8)
+  uint32_t pad;
+  uint64_t n;         // raw bits the output length refers to (8 S)
+  uint64_t m_cap;
+};
+struct MeBatchArgs {
+  const uint8_t* pool;
+  const MeBlock* blocks;  // device memory
+  int model, u_mode;
+  double mu, sigma;
+  double log2_inv_eps;
+  qrng_me_result* out;
+  uint64_t* m_out;
+};
+hipError_t minentropy_blocks(const MeBatchArgs& a, int nblocks, hipStream_t s);
 
 }  // namespace qrng

@@ -185,6 +185,15 @@ struct BitMap {
 };
 constexpr int MAXMAP = 8;
 
+// One transform (n+m-1 <= Nc): with the seed transformed as its first Nc
+// bits S, the raw block is placed rotated by d = n-1, x'[j'] = x[(j'+d) mod
+// Nc]; then (S * x')[t] = sum_j S[t+n-1-j] x[j] = row t of T x for t < m
+// (t+n-1-j stays inside [0, n+m-1), no wrap).  The rotation costs nothing
+// (it is a bit mapping), and the seed transform no longer depends on n, m.
+__host__ __device__ __forceinline__ BitMap rotated_block(uint32_t n, int32_t Nc) {
+  return BitMap{(int32_t)n - 1, 0, (int32_t)n, Nc - ((int32_t)n - 1)};
+}
+
 __device__ __forceinline__ uint32_t map_bit(const uint32_t* __restrict__ bits, const BitMap& mp,
                                             int32_t q, int32_t Nc) {
   const int32_t idx = mp.off + (q < mp.h ? q : q - Nc);
@@ -231,6 +240,7 @@ struct ColFwdArgs {
   int nmap;
   int log2, log_nc;
   uint32_t* out;  // item y = blockIdx.y at out + y * Nc
+  const NttItem* items;  // non-null: item y is the raw block items[y] (nmap = 1)
 };
 
 constexpr int COLS = 32;    // columns per workgroup (128-byte rows)
@@ -244,9 +254,16 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int32_t Nc = 1 << a.log_nc;
   const int j2 = blockIdx.x * COLS + c;
-  const int mi = blockIdx.y % a.nmap;
-  const uint32_t* __restrict__ bits = a.bits + (uint64_t)(blockIdx.y / a.nmap) * (a.zs >> 5);
-  const BitMap mp = a.map[mi];
+  const uint32_t* __restrict__ bits;
+  BitMap mp;
+  if (a.items) {
+    const NttItem& it = a.items[blockIdx.y];
+    bits = a.bits + (it.x_bit >> 5);
+    mp = rotated_block(it.n, Nc);
+  } else {
+    bits = a.bits + (uint64_t)(blockIdx.y / a.nmap) * (a.zs >> 5);
+    mp = a.map[blockIdx.y % a.nmap];
+  }
   uint32_t* __restrict__ out = a.out + (uint64_t)blockIdx.y * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   const int l2 = a.log2;
@@ -308,6 +325,8 @@ struct ColInvArgs {
   int64_t by;     // output chunk length
   uint64_t m;     // output bits the plan covers (words up to m are written)
   const uint64_t* m_dev;  // nullable: the valid output length, read on the device (<= m)
+  const NttItem* items;   // non-null: item y writes items[y] (ny = 1)
+  const uint64_t* m_arr;  // with items, nullable: valid length of item y at m_arr[blk]
 };
 
 // valid output bits: the plan's m, or the smaller length computed on the device
@@ -325,10 +344,21 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTable
   const int32_t Nc = 1 << a.log_nc;
   const int j2 = blockIdx.x * COLS + c;
   const int o = blockIdx.y % a.ny;
-  const uint64_t ybase = (uint64_t)(blockIdx.y / a.ny) * a.y_zs + (uint64_t)o * a.by;
-  const int64_t rem_cap = (int64_t)a.m - (int64_t)o * a.by;
+  uint64_t ybase, m;
+  const uint64_t* m_dev;
+  if (a.items) {
+    const NttItem& it = a.items[blockIdx.y];
+    ybase = it.y_bit;
+    m = it.m;
+    m_dev = a.m_arr ? a.m_arr + it.blk : nullptr;
+  } else {
+    ybase = (uint64_t)(blockIdx.y / a.ny) * a.y_zs + (uint64_t)o * a.by;
+    m = a.m;
+    m_dev = a.m_dev;
+  }
+  const int64_t rem_cap = (int64_t)m - (int64_t)o * a.by;
   const int32_t ylimit = ((int32_t)(rem_cap < a.by ? rem_cap : a.by) + 63) & ~63;
-  const int64_t rem = (int64_t)valid_bits(a.m, a.m_dev) - (int64_t)o * a.by;
+  const int64_t rem = (int64_t)valid_bits(m, m_dev) - (int64_t)o * a.by;
   const int32_t yvalid = (int32_t)(rem < a.by ? (rem < 0 ? 0 : rem) : a.by);
   uint32_t* __restrict__ ywords = a.y + (ybase >> 5);
   const uint32_t* __restrict__ in = a.in + (uint64_t)blockIdx.y * (uint32_t)Nc;
@@ -399,6 +429,8 @@ struct RowArgs {
   uint64_t y_zs;
   uint64_t m;
   const uint64_t* m_dev;  // nullable, as in ColInvArgs
+  const NttItem* items;   // hash with nx = ny = 1: item zy is items[zy] (raw block,
+  const uint64_t* m_arr;  // seed spectrum, output and valid length m_arr[blk])
 };
 
 // Threads of a row kernel: every thread owns GPT groups of the last round.
@@ -426,6 +458,7 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   const int row = blockIdx.x;
   const int zy = blockIdx.y;
   const int32_t Nc = 1 << a.log_nc;
+  const NttItem* desc = SEED ? nullptr : (a.items ? a.items + zy : nullptr);
 
   auto ld_lds_k = [&](auto kc) {
     return [&](int g, int e) -> uint32_t {
@@ -451,8 +484,9 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
     if constexpr (IN_BITS) {
       // the whole transform's input bits, 32 positions per LDS word
       __shared__ uint32_t wbits[N2 / 32];
-      const BitMap mp = a.map[SEED ? zy : c];
-      const uint32_t* __restrict__ bits = a.bits + (SEED ? 0 : (uint64_t)zy * (a.zs >> 5));
+      const BitMap mp = desc ? rotated_block(desc->n, Nc) : a.map[SEED ? zy : c];
+      const uint32_t* __restrict__ bits =
+          a.bits + (desc ? (desc->x_bit >> 5) : (SEED ? 0 : (uint64_t)zy * (a.zs >> 5)));
       for (int w = tid; w < N2 / 32; w += T) wbits[w] = stage_word(bits, mp, w * 32, Nc);
       __syncthreads();
       auto ld0 = [&](int g, int e) -> uint32_t {
@@ -461,7 +495,8 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
       };
       round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
     } else {
-      const uint32_t* __restrict__ src = a.in + (uint64_t)item * (uint32_t)Nc + (uint64_t)row * N2;
+      // no __restrict__: with one transform pass B works in place (in == out)
+      const uint32_t* src = a.in + (uint64_t)item * (uint32_t)Nc + (uint64_t)row * N2;
       auto ld0 = [&](int g, int e) -> uint32_t { return src[G0::pos0(g) + e * G0::s]; };
       round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
     }
@@ -505,7 +540,8 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
         for (int e = 0; e < 16; ++e) acc[u][e] = 0;
       static_for<0, NX>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        const uint32_t* wr = a.W + (uint64_t)(o - c + NX - 1) * (uint32_t)Nc + (uint64_t)row * N2;
+        const uint32_t* wr = (desc ? desc->W : a.W + (uint64_t)(o - c + NX - 1) * (uint32_t)Nc) +
+                             (uint64_t)row * N2;
 #pragma unroll
         for (int u = 0; u < GPT; ++u) {
           const uint32_t* wg = wr + (tid + u * T) * 16;
@@ -533,9 +569,12 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
       });
       if constexpr (OUT_BITS) {
         // the row is the whole transform: position q is output bit q
-        const int32_t yvalid = (int32_t)valid_bits(a.m, a.m_dev);
-        const int32_t ylimit = ((int32_t)a.m + 63) & ~63;
-        uint64_t* __restrict__ y64 = reinterpret_cast<uint64_t*>(a.y) + (uint64_t)zy * (a.y_zs >> 6);
+        const uint64_t m = desc ? desc->m : a.m;
+        const uint64_t* m_dev = desc ? (a.m_arr ? a.m_arr + desc->blk : nullptr) : a.m_dev;
+        const int32_t yvalid = (int32_t)valid_bits(m, m_dev);
+        const int32_t ylimit = ((int32_t)m + 63) & ~63;
+        uint64_t* __restrict__ y64 = reinterpret_cast<uint64_t*>(a.y) +
+                                     (desc ? (desc->y_bit >> 6) : (uint64_t)zy * (a.y_zs >> 6));
         auto st_bits = [&](int g, int e, uint32_t v) {
           const int q = G0::pos0(g) + e * G0::s;
           const uint32_t bit = (q < yvalid) ? (red1(v) & 1u) : 0u;
@@ -724,19 +763,28 @@ uint64_t ntt_seed_elems(const NttPlan& p) { return (uint64_t)p.nwin << p.log_nc;
 
 uint64_t ntt_work_elems(const NttPlan& p, int batch) {
   if (p.log1 == 0) return 0;
-  return (uint64_t)batch * (uint64_t)(p.nx + p.ny) << p.log_nc;
+  // one transform: pass B overwrites pass A's residues row by row
+  const uint64_t per = (p.nx == 1 && p.ny == 1) ? 1 : (uint64_t)(p.nx + p.ny);
+  return (uint64_t)batch * per << p.log_nc;
 }
 
 hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_t n,
-                            uint64_t m, uint32_t* W, uint32_t* work, const TwTables& tw,
-                            hipStream_t s) {
+                            uint64_t m, uint64_t seed_avail, uint32_t* W, uint32_t* work,
+                            const TwTables& tw, hipStream_t s) {
   const uint64_t L = n + m - 1;
   const int64_t Nc = (int64_t)1 << p.log_nc;
   if (p.nwin > MAXMAP) return hipErrorInvalidValue;
   BitMap maps[MAXMAP];
-  for (int w = 0; w < p.nwin; ++w) {
-    const int64_t d = w - (p.nx - 1);
-    maps[w] = BitMap{(int32_t)((int64_t)n - 1 + d * p.by), 0, (int32_t)L, (int32_t)p.by};
+  if (p.nx == 1 && p.ny == 1) {
+    // one transform: the first Nc seed bits, whatever n and m (the raw block
+    // carries the n-1 rotation, see ntt_hash)
+    const uint64_t hi = seed_avail < (uint64_t)Nc ? seed_avail : (uint64_t)Nc;
+    maps[0] = BitMap{0, 0, (int32_t)hi, (int32_t)Nc};
+  } else {
+    for (int w = 0; w < p.nwin; ++w) {
+      const int64_t d = w - (p.nx - 1);
+      maps[w] = BitMap{(int32_t)((int64_t)n - 1 + d * p.by), 0, (int32_t)L, (int32_t)p.by};
+    }
   }
   const uint32_t cw = (uint32_t)((uint64_t)host_pow(Nc % P, P - 2) * host_mont(host_mont(1)) % P);
   RowArgs r{};
@@ -782,11 +830,11 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   if (p.log1 == 0) {
     r.bits = x_bits;
     r.zs = x_stride_bits;
-    r.map[0] = BitMap{0, 0, (int32_t)n, (int32_t)Nc};
+    r.map[0] = rotated_block((uint32_t)n, (int32_t)Nc);
     return rows_l<1, true, false, true>(p.log2, r, dim3(1, batch), tw, s);
   }
   uint32_t* X = work;
-  uint32_t* Z = work + ((uint64_t)batch * p.nx << p.log_nc);
+  uint32_t* Z = (p.nx == 1 && p.ny == 1) ? X : work + ((uint64_t)batch * p.nx << p.log_nc);
   ColFwdArgs c{};
   c.bits = x_bits;
   c.zs = x_stride_bits;
@@ -795,6 +843,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
     const int64_t hi = lo + p.bx < (int64_t)n ? lo + p.bx : (int64_t)n;
     c.map[k] = BitMap{(int32_t)lo, (int32_t)lo, (int32_t)hi, (int32_t)Nc};
   }
+  if (p.nx == 1 && p.ny == 1) c.map[0] = rotated_block((uint32_t)n, (int32_t)Nc);
   c.nmap = p.nx;
   c.log2 = p.log2;
   c.log_nc = p.log_nc;
@@ -823,6 +872,51 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   ci.m = m;
   ci.m_dev = m_dev;
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, batch * p.ny), tw, s);
+}
+
+bool ntt_plan_for_length(int log_nc, NttPlan* p) {
+  if (log_nc < 10 || log_nc > LOG_MAX) return false;
+  const uint64_t Nc = 1ull << log_nc;
+  // n = m = Nc/2 gives L = Nc - 1, whose plan has exactly this length
+  return ntt_make_plan(Nc / 2, Nc / 2, p) && p->log_nc == log_nc;
+}
+
+hipError_t ntt_hash_items(const NttPlan& p, const uint32_t* x_pool, const NttItem* items,
+                          int count, uint32_t* y_pool, const uint64_t* m_arr, uint32_t* work,
+                          const TwTables& tw, hipStream_t s) {
+  if (p.nx != 1 || p.ny != 1) return hipErrorInvalidValue;
+  if (count <= 0) return hipSuccess;
+  RowArgs r{};
+  r.nx = r.ny = 1;
+  r.log_nc = p.log_nc;
+  r.y = y_pool;
+  r.bits = x_pool;
+  r.items = items;
+  r.m_arr = m_arr;
+  if (p.log1 == 0) return rows_l<1, true, false, true>(p.log2, r, dim3(1, count), tw, s);
+  ColFwdArgs c{};
+  c.bits = x_pool;
+  c.nmap = 1;
+  c.log2 = p.log2;
+  c.log_nc = p.log_nc;
+  c.out = work;
+  c.items = items;
+  hipError_t e = cols_fwd(p.log1, c, dim3((1u << p.log2) / COLS, count), tw, s);
+  if (e != hipSuccess) return e;
+  r.in = work;
+  r.out = work;
+  e = rows_l<1, false, false, false>(p.log2, r, dim3(1u << p.log1, count), tw, s);
+  if (e != hipSuccess) return e;
+  ColInvArgs ci{};
+  ci.in = work;
+  ci.ny = 1;
+  ci.log2 = p.log2;
+  ci.log_nc = p.log_nc;
+  ci.y = y_pool;
+  ci.by = (int64_t)1 << p.log_nc;
+  ci.items = items;
+  ci.m_arr = m_arr;
+  return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, count), tw, s);
 }
 
 }  // namespace qrng

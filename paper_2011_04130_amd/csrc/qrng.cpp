@@ -8,9 +8,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
+#include <set>
+#include <sstream>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -53,9 +57,17 @@ qrng_status fail(qrng_status st, const char* fmt, ...) {
 struct Seed {
   const uint64_t* ptr;
   uint64_t L;
-  // (n, m) -> transform-domain seed windows for the NTT path
+  uint32_t plans = 0;  // live plans that use this seed
+  // transform-domain seed windows for the NTT path: key (0, Nc) for one
+  // transform of length Nc (shared by every block shape that fits it), key
+  // (n, m) for the block-Toeplitz plans above 2^23 bits
   std::map<std::pair<uint64_t, uint64_t>, uint32_t*> spectra;
 };
+
+std::pair<uint64_t, uint64_t> spectra_key(const NttPlan& p, uint64_t n, uint64_t m) {
+  if (p.nx == 1 && p.ny == 1) return {0, 1ull << p.log_nc};
+  return {n, m};
+}
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
@@ -107,6 +119,11 @@ struct qrng_ctx {
   uint64_t* m_dev = nullptr;                  // and output-length slot
   std::map<uint32_t, Seed> seeds;
   uint32_t next_seed = 1;
+  std::set<qrng_plan*> plans;
+  // autotuned launch shape per transform-length class: (log2 Nc, ceil log2
+  // of the class size) -> sub-batch workspace cap as log2 bytes, or
+  // kTuneDirect for one direct launch per block
+  std::map<std::pair<int, int>, int> tune;
 };
 
 namespace {
@@ -209,8 +226,8 @@ qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t
   if (st) return st;
   if (!W) {
     uint32_t* Wt = ctx->work + work;
-    HIP_TRY(ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(seed), n, m, Wt, ctx->work,
-                             ctx->tw, s));
+    HIP_TRY(ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(seed), n, m, n + m - 1, Wt,
+                             ctx->work, ctx->tw, s));
     W = Wt;
   }
   HIP_TRY(ntt_hash(p, reinterpret_cast<const uint32_t*>(x), n, m, W,
@@ -221,16 +238,16 @@ qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t
 // Cached seed windows of a registered seed for shape (n, m).
 qrng_status seed_spectra(qrng_ctx* ctx, Seed& sd, uint64_t n, uint64_t m, hipStream_t s,
                          const uint32_t** out) {
-  auto key = std::make_pair(n, m);
+  NttPlan p;
+  if (!ntt_make_plan(n, m, &p))
+    return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
+                (unsigned long long)m);
+  const auto key = spectra_key(p, n, m);
   auto it = sd.spectra.find(key);
   if (it != sd.spectra.end()) {
     *out = it->second;
     return QRNG_OK;
   }
-  NttPlan p;
-  if (!ntt_make_plan(n, m, &p))
-    return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
-                (unsigned long long)m);
   uint32_t* W = nullptr;
   if (hipMalloc(&W, ntt_seed_elems(p) * 4) != hipSuccess)
     return fail(QRNG_ENOMEM, "seed spectra");
@@ -239,7 +256,7 @@ qrng_status seed_spectra(qrng_ctx* ctx, Seed& sd, uint64_t n, uint64_t m, hipStr
     (void)hipFree(W);
     return st;
   }
-  hipError_t e = ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(sd.ptr), n, m, W,
+  hipError_t e = ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(sd.ptr), n, m, sd.L, W,
                                   ctx->work, ctx->tw, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -455,6 +472,7 @@ void qrng_destroy(qrng_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
+  while (!c->plans.empty()) qrng_plan_destroy(*c->plans.begin());
   for (auto& kv : c->seeds)
     for (auto& sp : kv.second.spectra) (void)hipFree(sp.second);
   prof_release(c);
@@ -535,7 +553,7 @@ qrng_status qrng_seed_register(qrng_ctx* ctx, const uint64_t* seed, uint64_t L,
   if (!aligned8(seed)) return fail(QRNG_EINVAL, "seed must be 8-byte aligned");
   if (L == 0) return fail(QRNG_EINVAL, "empty seed");
   const uint32_t id = ctx->next_seed++;
-  ctx->seeds[id] = Seed{seed, L, {}};
+  ctx->seeds[id] = Seed{seed, L, 0, {}};
   *seed_id = id;
   return QRNG_OK;
 }
@@ -544,6 +562,8 @@ qrng_status qrng_seed_unregister(qrng_ctx* ctx, uint32_t seed_id) {
   if (!ctx) return fail(QRNG_EINVAL, "null context");
   auto it = ctx->seeds.find(seed_id);
   if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  if (it->second.plans)
+    return fail(QRNG_EBUSY, "seed %u is used by %u live plan(s)", seed_id, it->second.plans);
   DeviceGuard g(ctx->device);
   if (!it->second.spectra.empty()) HIP_TRY(hipDeviceSynchronize());
   for (auto& sp : it->second.spectra) (void)hipFree(sp.second);
@@ -729,6 +749,500 @@ qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
       i += cnt;
     }
   }
+  return QRNG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+// A plan fixes an uneven batch of blocks (Sec. III.E with per-block block
+// lengths and, optionally, per-block Sec. II estimates) once: descriptors
+// live in device memory, seed spectra are prepared, the launches are laid
+// out per transform-length class and may be replayed as one HIP graph.
+
+struct qrng_plan {
+  qrng_ctx* ctx = nullptr;
+  std::vector<uint32_t> seed_ids;  // seeds pinned while the plan lives
+  std::vector<std::function<hipError_t(hipStream_t)>> steps;
+  void* desc = nullptr;      // device: NttItem[] then MeBlock[]
+  uint32_t* work = nullptr;  // device workspace owned by the plan
+  uint64_t work_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t nblocks = 0, classes = 0;
+};
+
+namespace {
+
+constexpr int kTuneDirect = -1;
+constexpr int kTuneDefaultCap = 27;  // 128 MiB of transform residues per launch
+constexpr int kTuneNoCap = 40;
+
+struct ClassInfo {
+  int log_nc;
+  std::vector<uint32_t> ids;  // block indices
+  uint64_t item_off;          // first NttItem of the class in the device array
+  uint64_t max_n;
+};
+
+// Sub-batches of a class under a workspace cap of 2^cap_log2 bytes.
+int class_chunk(const NttPlan& p, size_t count, int cap_log2) {
+  const uint64_t per = ntt_work_elems(p, 1) * 4;
+  if (per == 0 || cap_log2 >= kTuneNoCap) return (int)std::min<size_t>(count, 1u << 16);
+  const uint64_t c = std::max<uint64_t>(1, (1ull << cap_log2) / per);
+  return (int)std::min<uint64_t>({c, (uint64_t)count, 1u << 16});
+}
+
+struct PlanBuild {
+  qrng_ctx* ctx;
+  const qrng_block* blocks;
+  const uint64_t* x_pool;
+  uint64_t* y_pool;
+  const uint64_t* m_arr;  // device valid lengths (estimate mode) or null
+  const NttItem* items_dev;
+  std::vector<ClassInfo> classes;
+  std::vector<uint32_t> singles;  // blocks hashed one launch each
+  std::vector<int> single_path;
+};
+
+// Launch steps of one class under a given shape choice; *work_need gets the
+// workspace (bytes) they use.
+void class_steps(const PlanBuild& b, const ClassInfo& c, int choice, uint32_t** work_slot,
+                 std::vector<std::function<hipError_t(hipStream_t)>>* out,
+                 uint64_t* work_need) {
+  qrng_ctx* ctx = b.ctx;
+  NttPlan p;
+  ntt_plan_for_length(c.log_nc, &p);
+  *work_need = 0;
+  if (choice == kTuneDirect) {
+    for (uint32_t id : c.ids) {
+      const qrng_block blk = b.blocks[id];
+      const uint64_t* seed = ctx->seeds[blk.seed_id].ptr;
+      const uint64_t* md = b.m_arr ? b.m_arr + id : nullptr;
+      const uint64_t* x = b.x_pool + blk.x_word_off;
+      uint64_t* y = b.y_pool + blk.y_word_off;
+      *work_need = std::max<uint64_t>(*work_need, direct_work_words(blk.n, 1) * 4);
+      const int ncu = ctx->num_cus;
+      out->push_back([=](hipStream_t s) {
+        return direct_hash(reinterpret_cast<const uint32_t*>(x), blk.n,
+                           reinterpret_cast<const uint32_t*>(seed), blk.m,
+                           reinterpret_cast<uint32_t*>(y), *work_slot, ncu, s, 1, 0, 0, md);
+      });
+    }
+    return;
+  }
+  const int chunk = class_chunk(p, c.ids.size(), choice);
+  const TwTables tw = ctx->tw;
+  for (size_t i = 0; i < c.ids.size(); i += chunk) {
+    const int cnt = (int)std::min<size_t>(chunk, c.ids.size() - i);
+    *work_need = std::max<uint64_t>(*work_need, ntt_work_elems(p, cnt) * 4);
+    const NttItem* items = b.items_dev + c.item_off + i;
+    const uint32_t* xp = reinterpret_cast<const uint32_t*>(b.x_pool);
+    uint32_t* yp = reinterpret_cast<uint32_t*>(b.y_pool);
+    const uint64_t* ma = b.m_arr;
+    out->push_back([=](hipStream_t s) {
+      return ntt_hash_items(p, xp, items, cnt, yp, ma, *work_slot, tw, s);
+    });
+  }
+}
+
+int tune_key_count(size_t count) {
+  int k = 0;
+  while ((size_t(1) << k) < count) ++k;
+  return k;
+}
+
+// Run `steps` eagerly: warm-up once, then the median of three timed runs (ms).
+qrng_status time_steps(const std::vector<std::function<hipError_t(hipStream_t)>>& steps,
+                       hipStream_t s, float* ms) {
+  hipEvent_t a = nullptr, e = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(QRNG_EDEVICE, "event");
+  }
+  float t[3] = {0, 0, 0};
+  hipError_t err = hipSuccess;
+  for (int r = -1; r < 3 && err == hipSuccess; ++r) {
+    err = hipEventRecord(a, s);
+    for (auto& f : steps)
+      if (err == hipSuccess) err = f(s);
+    if (err == hipSuccess) err = hipEventRecord(e, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e);
+    if (err == hipSuccess && r >= 0) err = hipEventElapsedTime(&t[r], a, e);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(QRNG_EDEVICE, "tuning run: %s", hipGetErrorString(err));
+  std::sort(t, t + 3);
+  *ms = t[1];
+  return QRNG_OK;
+}
+
+qrng_status plan_alloc_work(qrng_plan* pl, uint64_t bytes) {
+  if (bytes <= pl->work_bytes) return QRNG_OK;
+  if (pl->work) {
+    HIP_TRY(hipDeviceSynchronize());
+    (void)hipFree(pl->work);
+    pl->work = nullptr;
+    pl->work_bytes = 0;
+  }
+  if (hipMalloc(&pl->work, bytes) != hipSuccess)
+    return fail(QRNG_ENOMEM, "plan workspace of %llu bytes", (unsigned long long)bytes);
+  pl->work_bytes = bytes;
+  return QRNG_OK;
+}
+
+void plan_free(qrng_plan* pl) {
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->desc) (void)hipFree(pl->desc);
+  if (pl->work) (void)hipFree(pl->work);
+  for (uint32_t id : pl->seed_ids) {
+    auto it = pl->ctx->seeds.find(id);
+    if (it != pl->ctx->seeds.end() && it->second.plans) --it->second.plans;
+  }
+  pl->ctx->plans.erase(pl);
+  delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t nblocks,
+                             const uint64_t* x_pool, uint64_t* y_pool, uint64_t* m_dev,
+                             qrng_me_result* me_dev, const qrng_me_opts* opts,
+                             double log2_inv_eps, int path, uint32_t flags, void* stream,
+                             qrng_plan** out) {
+  if (!out) return fail(QRNG_EINVAL, "null plan handle");
+  *out = nullptr;
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  if (!blocks || !x_pool || !y_pool || nblocks == 0)
+    return fail(QRNG_EINVAL, "a plan needs blocks and both pools");
+  if (flags & ~(uint32_t)(QRNG_PLAN_ESTIMATE | QRNG_PLAN_GRAPH | QRNG_PLAN_TUNE))
+    return fail(QRNG_EINVAL, "unknown plan flags 0x%x", flags);
+  if (!aligned8(x_pool) || !aligned8(y_pool) || (m_dev && !aligned8(m_dev)) ||
+      (me_dev && !aligned8(me_dev)))
+    return fail(QRNG_EINVAL, "buffers must be 8-byte aligned");
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  const bool estimate = (flags & QRNG_PLAN_ESTIMATE) != 0;
+  if (estimate) {
+    if (!opts || !m_dev) return fail(QRNG_EINVAL, "estimate plans need opts and m_dev");
+    if (opts->sample_bits != 8) return fail(QRNG_EINVAL, "estimate plans take 8-bit samples");
+    if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
+      return fail(QRNG_EINVAL, "unknown model");
+    if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
+      return fail(QRNG_EINVAL, "unknown U mode");
+    if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
+    if (opts->model == QRNG_MODEL_GIVEN &&
+        !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
+      return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+    if (std::isnan(log2_inv_eps) || log2_inv_eps < 0)
+      return fail(QRNG_EINVAL, "bad security parameter");
+  }
+  // validate every descriptor
+  std::vector<std::pair<uint64_t, uint64_t>> yr;
+  yr.reserve(nblocks);
+  std::set<uint32_t> used;
+  for (uint32_t i = 0; i < nblocks; ++i) {
+    const qrng_block& b = blocks[i];
+    if (b.flags) return fail(QRNG_EINVAL, "block %u: flags must be 0", i);
+    if (b.n == 0 || b.m > b.n) return fail(QRNG_EINVAL, "block %u: need 0 < n and m <= n", i);
+    if (b.n >= (1ull << 32)) return fail(QRNG_EINVAL, "block %u: n must be < 2^32", i);
+    auto it = ctx->seeds.find(b.seed_id);
+    if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "block %u: unknown seed %u", i, b.seed_id);
+    if (b.m && b.n + b.m - 1 > it->second.L)
+      return fail(QRNG_EINVAL, "block %u: seed too short", i);
+    if (estimate && (b.n & 63)) return fail(QRNG_EINVAL, "block %u: n must be a multiple of 64", i);
+    if (b.m) yr.emplace_back(b.y_word_off, b.y_word_off + words64(b.m));
+    used.insert(b.seed_id);
+  }
+  std::sort(yr.begin(), yr.end());
+  for (size_t i = 1; i < yr.size(); ++i)
+    if (yr[i].first < yr[i - 1].second) return fail(QRNG_EINVAL, "output ranges overlap");
+
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  qrng_plan* pl = new qrng_plan();
+  pl->ctx = ctx;
+  pl->nblocks = nblocks;
+  ctx->plans.insert(pl);
+  for (uint32_t id : used) {
+    ctx->seeds[id].plans++;
+    pl->seed_ids.push_back(id);
+  }
+  auto bail = [&](qrng_status st) {
+    plan_free(pl);
+    return st;
+  };
+
+  // classes: one transform of length Nc per block where possible
+  PlanBuild b{ctx, blocks, x_pool, y_pool, estimate ? m_dev : nullptr, nullptr, {}, {}, {}};
+  std::map<int, size_t> cls_of;
+  for (uint32_t i = 0; i < nblocks; ++i) {
+    const qrng_block& bl = blocks[i];
+    if (!bl.m) continue;
+    int p = path == QRNG_PATH_AUTO ? choose_path(bl.n, bl.m) : path;
+    NttPlan np;
+    const bool one = ntt_make_plan(bl.n, bl.m, &np) && np.nx == 1 && np.ny == 1;
+    if ((path == QRNG_PATH_AUTO || path == QRNG_PATH_NTT) && one &&
+        (p == QRNG_PATH_NTT || path == QRNG_PATH_AUTO)) {
+      auto f = cls_of.find(np.log_nc);
+      if (f == cls_of.end()) {
+        f = cls_of.emplace(np.log_nc, b.classes.size()).first;
+        b.classes.push_back(ClassInfo{np.log_nc, {}, 0, 0});
+      }
+      ClassInfo& c = b.classes[f->second];
+      c.ids.push_back(i);
+      c.max_n = std::max<uint64_t>(c.max_n, bl.n);
+    } else {
+      b.singles.push_back(i);
+      b.single_path.push_back(p);
+    }
+  }
+  pl->classes = (uint32_t)b.classes.size();
+
+  // seed spectra (computed now, cached in the context) and item records
+  std::vector<NttItem> items;
+  for (ClassInfo& c : b.classes) {
+    c.item_off = items.size();
+    for (uint32_t id : c.ids) {
+      const qrng_block& bl = blocks[id];
+      const uint32_t* W = nullptr;
+      qrng_status st = seed_spectra(ctx, ctx->seeds[bl.seed_id], bl.n, bl.m, s, &W);
+      if (st) return bail(st);
+      items.push_back(NttItem{bl.x_word_off * 64, bl.y_word_off * 64, W, (uint32_t)bl.n,
+                              (uint32_t)bl.m, id, 0});
+    }
+  }
+  for (size_t k = 0; k < b.singles.size(); ++k)
+    if (b.single_path[k] == QRNG_PATH_NTT) {
+      const qrng_block& bl = blocks[b.singles[k]];
+      const uint32_t* W = nullptr;
+      qrng_status st = seed_spectra(ctx, ctx->seeds[bl.seed_id], bl.n, bl.m, s, &W);
+      if (st) return bail(st);
+    }
+  std::vector<MeBlock> meb;
+  if (estimate)
+    for (uint32_t i = 0; i < nblocks; ++i)
+      meb.push_back(MeBlock{blocks[i].x_word_off * 8, (uint32_t)(blocks[i].n / 8), 0, blocks[i].n,
+                            blocks[i].m});
+  const uint64_t ib = items.size() * sizeof(NttItem), mb = meb.size() * sizeof(MeBlock);
+  if (ib + mb) {
+    if (hipMalloc(&pl->desc, ib + mb) != hipSuccess) return bail(fail(QRNG_ENOMEM, "descriptors"));
+    if (ib && hipMemcpy(pl->desc, items.data(), ib, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(QRNG_EDEVICE, "descriptor upload"));
+    if (mb && hipMemcpy((char*)pl->desc + ib, meb.data(), mb, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(QRNG_EDEVICE, "descriptor upload"));
+  }
+  b.items_dev = reinterpret_cast<const NttItem*>(pl->desc);
+
+  // step 1: the per-block estimates
+  std::vector<std::function<hipError_t(hipStream_t)>> head;
+  if (estimate) {
+    MeBatchArgs a{};
+    a.pool = reinterpret_cast<const uint8_t*>(x_pool);
+    a.blocks = reinterpret_cast<const MeBlock*>((char*)pl->desc + ib);
+    a.model = opts->model;
+    a.u_mode = opts->u_mode;
+    a.mu = opts->mu;
+    a.sigma = opts->sigma;
+    a.log2_inv_eps = log2_inv_eps;
+    a.out = me_dev;
+    a.m_out = m_dev;
+    const int nb = (int)nblocks;
+    head.push_back([=](hipStream_t st) { return minentropy_blocks(a, nb, st); });
+  }
+
+  // step 2: each class, in the tuned (or default) launch shape
+  uint32_t** slot = &pl->work;
+  // default shape: batched transforms, except classes of short blocks, where
+  // the direct product wins (the single-block crossover near n = 2^15)
+  std::vector<int> choice(b.classes.size(), kTuneDefaultCap);
+  for (size_t k = 0; k < b.classes.size(); ++k) {
+    const ClassInfo& c = b.classes[k];
+    if (path == QRNG_PATH_AUTO && c.max_n < (1u << 15)) choice[k] = kTuneDirect;
+    auto t = ctx->tune.find({c.log_nc, tune_key_count(c.ids.size())});
+    if (t != ctx->tune.end() && (path == QRNG_PATH_AUTO || t->second != kTuneDirect))
+      choice[k] = t->second;
+  }
+  if (flags & QRNG_PLAN_TUNE) {
+    // the estimates decide the valid lengths the hashes read: run them once
+    for (auto& f : head) {
+      hipError_t e = f(s);
+      if (e != hipSuccess) return bail(fail(QRNG_EDEVICE, "estimate: %s", hipGetErrorString(e)));
+    }
+    for (size_t k = 0; k < b.classes.size(); ++k) {
+      const ClassInfo& c = b.classes[k];
+      std::vector<int> cand = {kTuneNoCap, 30, 28, 27, 26, 24};
+      if (path == QRNG_PATH_AUTO && c.max_n <= (1u << 16)) cand.push_back(kTuneDirect);
+      float best = INFINITY;
+      int best_c = choice[k];
+      int last_chunk = -1;
+      for (int cc : cand) {
+        NttPlan np;
+        ntt_plan_for_length(c.log_nc, &np);
+        if (cc != kTuneDirect) {
+          const int ch = class_chunk(np, c.ids.size(), cc);
+          if (ch == last_chunk) continue;  // same launch shape as the previous cap
+          last_chunk = ch;
+        }
+        std::vector<std::function<hipError_t(hipStream_t)>> st;
+        uint64_t need = 0;
+        class_steps(b, c, cc, slot, &st, &need);
+        if (need > (8ull << 30)) continue;  // keep tuning runs within 8 GiB
+        qrng_status e = plan_alloc_work(pl, need);
+        if (e) return bail(e);
+        float ms = 0;
+        e = time_steps(st, s, &ms);
+        if (e) return bail(e);
+        if (ms < best) best = ms, best_c = cc;
+      }
+      choice[k] = best_c;
+      ctx->tune[{c.log_nc, tune_key_count(c.ids.size())}] = best_c;
+    }
+  }
+  uint64_t work_need = 0;
+  pl->steps = head;
+  for (size_t k = 0; k < b.classes.size(); ++k) {
+    uint64_t need = 0;
+    class_steps(b, b.classes[k], choice[k], slot, &pl->steps, &need);
+    work_need = std::max(work_need, need);
+  }
+  // blocks that need the split transform (or a forced path): one launch each
+  for (size_t k = 0; k < b.singles.size(); ++k) {
+    const uint32_t id = b.singles[k];
+    const qrng_block bl = blocks[id];
+    Seed& sd = ctx->seeds[bl.seed_id];
+    const uint64_t* md = b.m_arr ? b.m_arr + id : nullptr;
+    const uint32_t* x = reinterpret_cast<const uint32_t*>(x_pool + bl.x_word_off);
+    uint32_t* y = reinterpret_cast<uint32_t*>(y_pool + bl.y_word_off);
+    const uint32_t* seed = reinterpret_cast<const uint32_t*>(sd.ptr);
+    const int p = b.single_path[k];
+    if (p == QRNG_PATH_NTT) {
+      NttPlan np;
+      if (!ntt_make_plan(bl.n, bl.m, &np))
+        return bail(fail(QRNG_EUNSUPPORTED, "block %u: NTT path cannot hash this shape", id));
+      const uint32_t* W = nullptr;
+      qrng_status st = seed_spectra(ctx, sd, bl.n, bl.m, s, &W);
+      if (st) return bail(st);
+      work_need = std::max<uint64_t>(work_need, ntt_work_elems(np, 1) * 4);
+      const TwTables tw = ctx->tw;
+      pl->steps.push_back([=](hipStream_t st) {
+        return ntt_hash(np, x, bl.n, bl.m, W, y, *slot, 1, 0, 0, tw, st, md);
+      });
+    } else if (p == QRNG_PATH_DIRECT) {
+      work_need = std::max<uint64_t>(work_need, direct_work_words(bl.n, 1) * 4);
+      const int ncu = ctx->num_cus;
+      pl->steps.push_back([=](hipStream_t st) {
+        return direct_hash(x, bl.n, seed, bl.m, y, *slot, ncu, st, 1, 0, 0, md);
+      });
+    } else {
+      pl->steps.push_back([=](hipStream_t st) {
+        return mfma_hash(x, bl.n, seed, bl.m, y, 1, 0, 0, st, md);
+      });
+    }
+  }
+  // the workspace now fits the chosen shapes (tuning may have left it larger)
+  if (pl->work_bytes > 2 * work_need + (64u << 20)) {
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipFree(pl->work);
+    pl->work = nullptr;
+    pl->work_bytes = 0;
+  }
+  qrng_status st = plan_alloc_work(pl, std::max<uint64_t>(work_need, 256));
+  if (st) return bail(st);
+
+  if (flags & QRNG_PLAN_GRAPH) {
+    // capture on a private stream, with the timing hooks off (no event nodes)
+    HIP_TRY(hipStreamSynchronize(s));
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(QRNG_EDEVICE, "capture stream"));
+    CtxScope off(nullptr);
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    for (auto& f : pl->steps)
+      if (e == hipSuccess) e = f(cap);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap, &gr);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, gr, nullptr, nullptr, 0);
+    pl->graph = gr;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return bail(fail(QRNG_EDEVICE, "graph capture: %s", hipGetErrorString(e)));
+  }
+  *out = pl;
+  return QRNG_OK;
+}
+
+qrng_status qrng_plan_execute(qrng_plan* pl, void* stream) {
+  if (!pl) return fail(QRNG_EINVAL, "null plan");
+  DeviceGuard g(pl->ctx->device);
+  CtxScope cs(pl->ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (pl->exec) {
+    HIP_TRY(hipGraphLaunch(pl->exec, s));
+    return QRNG_OK;
+  }
+  for (auto& f : pl->steps) {
+    const hipError_t e = f(s);
+    if (e != hipSuccess) return fail(QRNG_EDEVICE, "plan step: %s", hipGetErrorString(e));
+  }
+  return QRNG_OK;
+}
+
+qrng_status qrng_plan_query(const qrng_plan* pl, qrng_plan_info* info) {
+  if (!pl || !info) return fail(QRNG_EINVAL, "null argument");
+  info->blocks = pl->nblocks;
+  info->classes = pl->classes;
+  info->launches = (uint32_t)pl->steps.size();
+  info->graph = pl->exec ? 1u : 0u;
+  info->workspace_bytes = pl->work_bytes;
+  return QRNG_OK;
+}
+
+void qrng_plan_destroy(qrng_plan* pl) {
+  if (!pl) return;
+  DeviceGuard g(pl->ctx->device);
+  (void)hipDeviceSynchronize();
+  plan_free(pl);
+}
+
+qrng_status qrng_tune_export(qrng_ctx* ctx, char* buf, uint64_t cap, uint64_t* len) {
+  if (!ctx || !len) return fail(QRNG_EINVAL, "null argument");
+  std::ostringstream os;
+  for (auto& kv : ctx->tune)
+    os << "ntt " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+  const std::string t = os.str();
+  *len = t.size();
+  if (buf) {
+    if (cap < t.size() + 1) return fail(QRNG_EINVAL, "buffer holds %llu bytes, need %llu",
+                                        (unsigned long long)cap, (unsigned long long)(t.size() + 1));
+    std::memcpy(buf, t.c_str(), t.size() + 1);
+  }
+  return QRNG_OK;
+}
+
+qrng_status qrng_tune_import(qrng_ctx* ctx, const char* text) {
+  if (!ctx || !text) return fail(QRNG_EINVAL, "null argument");
+  std::istringstream is(text);
+  std::string line;
+  std::map<std::pair<int, int>, int> add;
+  int ln = 0;
+  while (std::getline(is, line)) {
+    ++ln;
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream ls(line);
+    std::string tag;
+    int a = 0, c = 0, v = 0;
+    if (!(ls >> tag >> a >> c >> v) || tag != "ntt" || a < 10 || a > 23 || c < 0 || c > 32 ||
+        !(v == kTuneDirect || (v >= 10 && v <= kTuneNoCap)))
+      return fail(QRNG_EINVAL, "tuning table line %d is malformed", ln);
+    add[{a, c}] = v;
+  }
+  for (auto& kv : add) ctx->tune[kv.first] = kv.second;
   return QRNG_OK;
 }
 

@@ -111,6 +111,30 @@ def batched_shapes(cfg: dict) -> dict:
     return {"n": n, "sigma": sig}
 
 
+def batched_pool(cfg: dict) -> dict:
+    """Sample pool of the uneven batched workload.
+
+    Block b draws n_b / 8 samples with ``gen_adc(sigma=sigma_b, seed=adc_seed
+    + b)``; blocks are concatenated in order (n_b is a multiple of 64, so each
+    block starts 8-byte aligned).  Block b uses seed group b // group, whose
+    seed words are ``gen_seed_words(seed_bits, seed_seed + g)`` with
+    seed_bits = 2 max(n) (enough for any m <= n).
+    """
+    sh = batched_shapes(cfg)
+    n, sig = sh["n"], sh["sigma"]
+    S = n // 8
+    off = np.concatenate([[0], np.cumsum(S)[:-1]]).astype(np.int64)
+    pool = np.empty(int(S.sum()), dtype=np.uint8)
+    for b in range(len(n)):
+        pool[off[b]:off[b] + S[b]] = gen_adc(int(S[b]), float(sig[b]), seed=cfg["adc_seed"] + b)
+    group = cfg["group"]
+    ngroups = (len(n) + group - 1) // group
+    return {"n": n, "sigma": sig, "samples": pool, "byte_off": off,
+            "seed_of": np.arange(len(n)) // group, "nseeds": ngroups,
+            "seed_bits": int(2 * n.max()),
+            "seed_words": lambda g: gen_seed_words(int(2 * n.max()), cfg["seed_seed"] + g)}
+
+
 def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
     """Arrival times (seconds) of an open-loop Poisson process."""
     rng = np.random.default_rng(seed)
