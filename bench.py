@@ -12,9 +12,11 @@ Workload (default): one block of 2^20 Gaussian samples (mean 128, sigma 20)
 
 Prints ONE JSON line.  `value` is raw input bits hashed per second (Gbit/s)
 with inputs resident in HBM.  `roofline` describes the kernel that takes the
-most device time inside the timed region (timed there with HIP events on its
-own stream); `cpu_baseline` times the CPU oracle on a bounded sample of the
-same block.  Usage: python bench.py [--steps K] [--warmup W] [--path ntt|direct]
+most device time per step (timed with HIP events recorded around each of its
+launches on its own stream, over a second pass of the same K steps, so the
+events do not slow the pass that gives `value`); `cpu_baseline` times the CPU
+oracle on a bounded sample of the same block.  Extras: the 4096-block uneven
+plan and the block-length sweep over a 2^30-bit sequence.  Usage: python bench.py [--steps K] [--warmup W] [--path ntt|direct]
 """
 import argparse
 import hashlib
@@ -157,6 +159,106 @@ def cpu_baseline(xw, n, sw, m, seconds=12.0):
                       % (rows_done - 1, m, t_used)}
 
 
+def _dev_words(torch, w):
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(w).view(np.int64).copy()).to("cuda:0")
+
+
+def _time_fn(torch, fn, reps):
+    """Median device time (s) of fn() over reps runs, bracketed by events
+    on torch's current stream (where the library enqueues)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_uneven(ctx, q, torch, qi, reps=10):
+    """4096 uneven blocks (n log-uniform in [2^14, 2^20], 64 seeds), each with
+    its own min-entropy estimate and output length, as one plan (HIP graph
+    replay after the launch shapes are tuned)."""
+    import numpy as np
+    cfg = qi.config(3)
+    pool = qi.batched_pool(cfg)
+    ns, offs = pool["n"], pool["byte_off"]
+    sids = [ctx.register_seed(_dev_words(torch, pool["seed_words"](g)), pool["seed_bits"])
+            for g in range(pool["nseeds"])]
+    rows, yo = [], 0
+    for b in range(len(ns)):
+        rows.append((int(offs[b]) // 8, int(ns[b]), int(ns[b]), yo, sids[pool["seed_of"][b]]))
+        yo += (int(ns[b]) + 63) // 64
+    x = _dev_words(torch, qi.samples_as_words(pool["samples"]))
+    y = torch.empty(yo, dtype=torch.int64, device="cuda:0")
+    m_out = torch.zeros(len(ns), dtype=torch.int64, device="cuda:0")
+    out = {"workload": cfg["name"], "blocks": len(ns), "raw_bits": int(ns.sum())}
+    try:
+        t0 = time.perf_counter()
+        plan = ctx.plan(rows, x, y, m_out=m_out, estimate=True, graph=True, tune=True)
+        out["plan_create_s"] = round(time.perf_counter() - t0, 3)
+        info = plan.info()
+        t = _time_fn(torch, plan.execute, reps)
+        m_tot = int(m_out.sum().item())
+        eager = ctx.plan(rows, x, y, m_out=m_out, estimate=True, graph=False)
+        te = _time_fn(torch, eager.execute, reps)
+        ctx.profile(True)
+        ctx.profile_reset()
+        eager.execute()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        eager.close()
+        plan.close()
+        out.update({"ms_per_step": round(t * 1e3, 4), "raw_gbps": round(ns.sum() / t / 1e9, 3),
+                    "extracted_gbps": round(m_tot / t / 1e9, 3),
+                    "eager_ms_per_step": round(te * 1e3, 4),
+                    "classes": info["classes"], "launch_groups": info["launches"],
+                    "workspace_MiB": round(info["workspace_bytes"] / 2 ** 20, 1),
+                    "kernels_ms": {k: round(ms, 4) for k, (c, ms) in prof.items()},
+                    "tune_table": ctx.tune_export().strip().split("\n")})
+    finally:
+        for sid in sids:
+            ctx.unregister_seed(sid)
+    return out
+
+
+def bench_sweep(ctx, q, torch, qi, reps=3):
+    """A 2^30-bit raw sequence (2^27 ADC samples) cut into blocks of n = 2^12
+    .. 2^24 bits, every block hashed with one seed at m = 5n/8; raw Gbit/s per
+    path (direct only where it finishes quickly)."""
+    cfg = qi.config(2)
+    tot = cfg["total_bits"]
+    x = torch.from_numpy(qi.gen_adc(cfg["S"], cfg["sigma"], seed=cfg["adc_seed"])).to("cuda:0")
+    x = x.view(torch.int64)
+    res = {}
+    for lg in cfg["block_log2"]:
+        n = 1 << lg
+        m = n * cfg["gamma_num"] // cfg["gamma_den"]
+        B = tot // n
+        sid = ctx.register_seed(_dev_words(torch, qi.gen_seed_words(n + m - 1, cfg["seed_seed"])),
+                                n + m - 1)
+        yw = (m + 63) // 64
+        y = torch.empty(B * yw, dtype=torch.int64, device="cuda:0")
+        row = {}
+        for name, path in (("auto", q.PATH_AUTO), ("ntt", q.PATH_NTT), ("mfma", q.PATH_MFMA),
+                           ("direct", q.PATH_DIRECT)):
+            if name in ("mfma", "direct") and lg > 14:
+                continue
+            t = _time_fn(torch, lambda: ctx.hash_strided(x, n, n // 64, sid, m, y, yw, B,
+                                                          path=path), reps)
+            row[name] = round(tot / t / 1e9, 2)
+        ctx.unregister_seed(sid)
+        res["2^%d" % lg] = row
+    return {"workload": cfg["name"], "unit": "raw Gbit/s", "by_block_bits": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +268,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="oracle time budget for cpu_baseline (0 = skip)")
     ap.add_argument("--extras", type=int, default=1, help="also time the other paths")
+    ap.add_argument("--uneven", type=int, default=1, help="also time the 4096-block uneven plan")
+    ap.add_argument("--sweep", type=int, default=1, help="also time the block-length sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -218,14 +322,21 @@ def main():
     m = int(m_t.item())
     assert m == m_expect, "min-entropy gave m=%d, expected %d" % (m, m_expect)
     torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_reset()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same K steps again with every launch bracketed by HIP events on its
+    # stream: per-kernel device time (the brackets cost a few us per launch,
+    # so they stay out of the run that gives `value`)
+    ctx.profile(True)
+    ctx.profile_reset()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
     prof = ctx.profile_read()
     ctx.profile(False)
     ms_step = elapsed / args.steps * 1e3
@@ -257,6 +368,7 @@ def main():
                    "step": "qrng_extract: device histogram, min-entropy, m, hash"},
         "extracted_gbps": round(m / (elapsed / args.steps) / 1e9, 4),
         "kernels": kernels,
+        "ms_per_step_with_kernel_events": round(elapsed_prof / args.steps * 1e3, 4),
         "roofline": roof,
     }
 
@@ -285,6 +397,10 @@ def main():
             "ntt_seed_transformed_each_call": round(n / t_plain / 1e9, 3),
             "direct": round(n / t_direct / 1e9, 4)}
 
+    if args.uneven:
+        out["uneven_4096"] = bench_uneven(ctx, q, torch, qi)
+    if args.sweep:
+        out["sweep_2^30"] = bench_sweep(ctx, q, torch, qi)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(xw, n, sw, m, args.cpu_seconds)
     ctx.close()

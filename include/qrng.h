@@ -257,6 +257,103 @@ qrng_status qrng_tune_export(qrng_ctx *ctx, char *buf, uint64_t cap, uint64_t *l
  * nothing merged then). */
 qrng_status qrng_tune_import(qrng_ctx *ctx, const char *text);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of extraction requests over a stream of raw windows.
+ * The raw stream arrives in windows of W 8-bit samples (qrng_server_feed
+ * copies each into one of the server's window slots).  Each window gets one
+ * Sec. II estimate and is cut into blocks of n_s raw bits; each block hashes
+ * (Sec. III.B, the server's seed) to m_s output bits, m_s = n_s H/8 -
+ * ceil(2 log2(1/eps)) rounded down to a multiple of 64 (fewer rows of T are
+ * still an extractor).  A request for R bits takes ceil(R/m_s) consecutive
+ * unused blocks of ONE window (one estimate applies), and its output is their
+ * hashes concatenated and cut to R bits, contiguous in the server's output
+ * ring.  qrng_server_step admits queued requests first come first served
+ * while the ring has room for their outputs (admission by memory) and
+ * enqueues one hash launch per run of admitted blocks; a request whose head
+ * does not fit in the rest of the current window moves the server to the
+ * next window.  The bits a request receives depend only on the window and the
+ * blocks it was given, never on the other requests batched with it.
+ * A server belongs to one context and one host thread.  qrng_destroy
+ * destroys the context's servers. */
+typedef struct qrng_server qrng_server;
+
+typedef struct {
+  uint64_t window_samples; /* W: samples per window, a multiple of n_s / 8 */
+  uint64_t block_bits;     /* n_s: multiple of 512, or 0 = chosen by timing candidates */
+  uint64_t ring_bits;      /* output ring capacity, multiple of 64 */
+  uint32_t window_slots;   /* windows held at once (>= 2) */
+  uint32_t max_queue;      /* queued requests accepted (QRNG_EBUSY beyond) */
+  uint32_t seed_id;        /* registered seed with >= 2 n_s - 1 bits */
+  int32_t path;            /* hash path (QRNG_PATH_AUTO lets the library pick) */
+  qrng_me_opts opts;       /* estimate options; sample_bits must be 8 */
+  double log2_inv_eps;
+} qrng_server_cfg;
+
+typedef struct {
+  uint64_t request_id;
+  uint64_t bits;           /* R */
+  uint64_t ring_word;      /* output starts at word ring_word of the ring */
+  uint64_t window;         /* sequence number of the window (0, 1, ...) */
+  uint64_t first_block;    /* its first block in that window */
+  uint32_t blocks;         /* ceil(R / m_s) */
+  int32_t status;          /* QRNG_OK, or QRNG_EUNSUPPORTED if R can never fit */
+  uint64_t m_block;        /* m_s of that window */
+} qrng_served;
+
+typedef struct {
+  uint64_t block_bits, blocks_per_window;
+  uint64_t windows_fed, windows_used, blocks_hashed, bits_served;
+  uint64_t queued, in_flight, ring_free_bits;
+  uint64_t m_block;        /* m_s of the current window (0 before the first) */
+} qrng_server_stats;
+
+/* Create a server: allocates the window slots and the output ring, and
+ * with block_bits == 0 times the candidate block lengths on one window's
+ * worth of blocks (nominal H = 5 bits per sample) and keeps the one that
+ * extracts the most bits per second. */
+qrng_status qrng_server_create(qrng_ctx *ctx, const qrng_server_cfg *cfg, qrng_server **srv);
+
+/* Copy W samples from samples_dev into a free window slot, enqueued on
+ * `stream` after its earlier work, and enqueue the window's estimate.
+ * QRNG_EBUSY if every slot holds a window still in use. */
+qrng_status qrng_server_feed(qrng_server *srv, const uint8_t *samples_dev, void *stream);
+
+/* Queue a request for `bits` > 0 output bits; *request_id receives its id.
+ * QRNG_EBUSY if max_queue requests are already waiting. */
+qrng_status qrng_server_submit(qrng_server *srv, uint64_t bits, uint64_t *request_id);
+
+/* Admit what fits and enqueue the hashes (never waits for the GPU except
+ * for the estimate of a window it moves to).  *admitted (nullable) receives
+ * the number of requests admitted. */
+qrng_status qrng_server_step(qrng_server *srv, uint32_t *admitted);
+
+/* Completed requests, oldest first, up to cap; *count receives how many were
+ * written to out_host.  Their outputs are in the ring until released. */
+qrng_status qrng_server_poll(qrng_server *srv, qrng_served *out_host, uint32_t cap,
+                             uint32_t *count);
+
+/* Give a completed request's ring space back. */
+qrng_status qrng_server_release(qrng_server *srv, uint64_t request_id);
+
+/* Copy a completed request's R output bits (ceil(R/64) words, bits past R
+ * written as 0) to out_dev, enqueued on `stream`.  The ring space stays held
+ * until qrng_server_release. */
+qrng_status qrng_server_read(qrng_server *srv, uint64_t request_id, uint64_t *out_dev,
+                             void *stream);
+
+/* Device pointer of the output ring (ring_bits / 64 words). */
+qrng_status qrng_server_ring(qrng_server *srv, const uint64_t **ring_dev);
+
+/* Device pointer of window slot data for window `window` while it is held
+ * (for checking), and the slot's estimate (qrng_me_result, device memory). */
+qrng_status qrng_server_window(qrng_server *srv, uint64_t window, const uint8_t **samples_dev,
+                               const qrng_me_result **estimate_dev);
+
+qrng_status qrng_server_query(qrng_server *srv, qrng_server_stats *stats);
+
+/* Waits for the server's work, then frees it.  NULL is a no-op. */
+void qrng_server_destroy(qrng_server *srv);
+
 /* Measurement aid.  While enabled, every kernel the context launches is
  * bracketed by HIP events recorded on the stream it runs on (a few
  * microseconds of host overhead per launch; results are unchanged). */

@@ -55,6 +55,33 @@ class PlanInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("window_samples", ctypes.c_uint64), ("block_bits", ctypes.c_uint64),
+                ("ring_bits", ctypes.c_uint64), ("window_slots", ctypes.c_uint32),
+                ("max_queue", ctypes.c_uint32), ("seed_id", ctypes.c_uint32),
+                ("path", ctypes.c_int32), ("opts", MeOpts), ("log2_inv_eps", ctypes.c_double)]
+
+
+class Served(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("bits", ctypes.c_uint64),
+                ("ring_word", ctypes.c_uint64), ("window", ctypes.c_uint64),
+                ("first_block", ctypes.c_uint64), ("blocks", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("m_block", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("block_bits", "blocks_per_window", "windows_fed", "windows_used",
+                 "blocks_hashed", "bits_served", "queued", "in_flight", "ring_free_bits",
+                 "m_block")]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 # every symbol the header declares
@@ -64,6 +91,10 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
            "qrng_plan_create", "qrng_plan_execute", "qrng_plan_query", "qrng_plan_destroy",
            "qrng_tune_export", "qrng_tune_import",
+           "qrng_server_create", "qrng_server_feed", "qrng_server_submit", "qrng_server_step",
+           "qrng_server_poll", "qrng_server_release", "qrng_server_read", "qrng_server_ring",
+           "qrng_server_window",
+           "qrng_server_query", "qrng_server_destroy",
            "qrng_profile_enable", "qrng_profile_kernel_name",
            "qrng_profile_query", "qrng_profile_reset"]
 
@@ -121,6 +152,21 @@ def load_library(path: str | None = None):
     lib.qrng_tune_export.restype = i32
     lib.qrng_tune_import.argtypes = [vp, ctypes.c_char_p]
     lib.qrng_tune_import.restype = i32
+    lib.qrng_server_create.argtypes = [vp, ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+    lib.qrng_server_feed.argtypes = [vp, vp, vp]
+    lib.qrng_server_submit.argtypes = [vp, u64, ctypes.POINTER(u64)]
+    lib.qrng_server_step.argtypes = [vp, ctypes.POINTER(u32)]
+    lib.qrng_server_poll.argtypes = [vp, ctypes.POINTER(Served), u32, ctypes.POINTER(u32)]
+    lib.qrng_server_release.argtypes = [vp, u64]
+    lib.qrng_server_read.argtypes = [vp, u64, vp, vp]
+    lib.qrng_server_ring.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.qrng_server_window.argtypes = [vp, u64, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.qrng_server_query.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    for f in ("create", "feed", "submit", "step", "poll", "release", "read", "ring", "window",
+              "query"):
+        getattr(lib, "qrng_server_" + f).restype = i32
+    lib.qrng_server_destroy.argtypes = [vp]
+    lib.qrng_server_destroy.restype = None
     lib.qrng_profile_enable.argtypes = [vp, i32]
     lib.qrng_profile_enable.restype = i32
     lib.qrng_profile_kernel_name.argtypes = [i32]

@@ -10,8 +10,8 @@ from __future__ import annotations
 import ctypes
 
 from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, PLAN_ESTIMATE, PLAN_GRAPH, PLAN_TUNE,
-                   U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, check,
-                   kernel_names, load_library)
+                   U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, Served,
+                   ServerCfg, ServerStats, check, kernel_names, load_library)
 
 
 def _words(bits: int) -> int:
@@ -266,6 +266,18 @@ class Context:
                                          ctypes.byref(h)))
         return Plan(self, h, (x_pool, y_pool, m_out, me_out))
 
+    def server(self, seed_id: int, window_samples: int, block_bits: int = 0,
+               ring_bits: int = 1 << 30, window_slots: int = 4, max_queue: int = 1 << 16,
+               model: int = MODEL_FIT, mu: float = 0.0, sigma: float = 0.0,
+               u_mode: int = U_MODEL_ARGMAX, log2_inv_eps: float = 0.0,
+               path: int = PATH_AUTO) -> "Server":
+        """A qrng_server (continuous batching over windows of raw samples)."""
+        cfg = ServerCfg(window_samples, block_bits, ring_bits, window_slots, max_queue, seed_id,
+                        path, MeOpts(8, model, mu, sigma, u_mode, 0), log2_inv_eps)
+        h = ctypes.c_void_p()
+        check(self._lib.qrng_server_create(self._h, ctypes.byref(cfg), ctypes.byref(h)))
+        return Server(self, h)
+
     def tune_export(self) -> str:
         n = ctypes.c_uint64()
         check(self._lib.qrng_tune_export(self._h, None, 0, ctypes.byref(n)))
@@ -320,4 +332,92 @@ class Plan:
             pass
 
 
-__all__ = ["Context", "Plan", "QrngError"]
+class Server:
+    """Serving loop on one context (see Context.server)."""
+
+    def __init__(self, ctx: Context, handle):
+        self._ctx = ctx
+        self._h = handle
+        self._lib = ctx._lib
+
+    def feed(self, samples, stream=None) -> None:
+        torch = self._ctx._torch
+        p = self._ctx._dev_tensor(samples, "samples", torch.uint8)
+        check(self._lib.qrng_server_feed(self._h, p, _stream(torch, self._ctx.device, stream)))
+
+    def try_feed(self, samples, stream=None) -> bool:
+        """feed(), but False instead of an error when every slot is busy."""
+        try:
+            self.feed(samples, stream)
+            return True
+        except QrngError as e:
+            if e.status == -5:
+                return False
+            raise
+
+    def submit(self, bits: int) -> int:
+        rid = ctypes.c_uint64()
+        check(self._lib.qrng_server_submit(self._h, bits, ctypes.byref(rid)))
+        return rid.value
+
+    def step(self) -> int:
+        n = ctypes.c_uint32()
+        check(self._lib.qrng_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, cap: int = 4096) -> list:
+        arr = (Served * cap)()
+        n = ctypes.c_uint32()
+        check(self._lib.qrng_server_poll(self._h, arr, cap, ctypes.byref(n)))
+        return [arr[i].as_dict() for i in range(n.value)]
+
+    def release(self, request_id: int) -> None:
+        check(self._lib.qrng_server_release(self._h, request_id))
+
+    def read(self, request_id: int, bits: int, out=None, stream=None):
+        """A completed request's output bits as an int64 word tensor."""
+        torch = self._ctx._torch
+        if out is None:
+            out = torch.empty((bits + 63) // 64, dtype=torch.int64,
+                              device="cuda:%d" % self._ctx.device)
+        if out.numel() * out.element_size() < (bits + 63) // 64 * 8:
+            raise ValueError("output buffer too small")
+        p = self._ctx._dev_tensor(out, "out")
+        check(self._lib.qrng_server_read(self._h, request_id, p,
+                                         _stream(torch, self._ctx.device, stream)))
+        return out
+
+    def ring_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        check(self._lib.qrng_server_ring(self._h, ctypes.byref(p)))
+        return p.value
+
+    def window_estimate_ptr(self, window: int) -> int:
+        s, e = ctypes.c_void_p(), ctypes.c_void_p()
+        check(self._lib.qrng_server_window(self._h, window, ctypes.byref(s), ctypes.byref(e)))
+        return e.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(self._lib.qrng_server_query(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and getattr(self._ctx, "_h", None):
+            self._lib.qrng_server_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["Context", "Plan", "Server", "QrngError"]

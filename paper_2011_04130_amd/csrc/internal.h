@@ -148,4 +148,17 @@ struct MeBatchArgs {
 };
 hipError_t minentropy_blocks(const MeBatchArgs& a, int nblocks, hipStream_t s);
 
+// ------------------------------------------------- context services
+// (for the serving loop, which is built on the C ABI)
+int ctx_num_cus(const qrng_ctx* c);
+int ctx_device(const qrng_ctx* c);
+// delta = +1 / -1 pins / unpins a registered seed (pinned seeds cannot be
+// unregistered), 0 only looks it up; *L (nullable) receives its length.
+// false if the id is unknown.
+bool ctx_pin_seed(qrng_ctx* c, uint32_t seed_id, int delta, uint64_t* L);
+// Servers are destroyed with their context.
+void ctx_track_server(qrng_ctx* c, qrng_server* s, bool add);
+// Records the last error text (returns st).
+qrng_status set_error(qrng_status st, const char* fmt, ...);
+
 }  // namespace qrng

@@ -57,7 +57,7 @@ qrng_status fail(qrng_status st, const char* fmt, ...) {
 struct Seed {
   const uint64_t* ptr;
   uint64_t L;
-  uint32_t plans = 0;  // live plans that use this seed
+  uint32_t plans = 0;  // live plans and servers that use this seed
   // transform-domain seed windows for the NTT path: key (0, Nc) for one
   // transform of length Nc (shared by every block shape that fits it), key
   // (n, m) for the block-Toeplitz plans above 2^23 bits
@@ -120,6 +120,7 @@ struct qrng_ctx {
   std::map<uint32_t, Seed> seeds;
   uint32_t next_seed = 1;
   std::set<qrng_plan*> plans;
+  std::set<qrng_server*> servers;
   // autotuned launch shape per transform-length class: (log2 Nc, ceil log2
   // of the class size) -> sub-batch workspace cap as log2 bytes, or
   // kTuneDirect for one direct launch per block
@@ -191,10 +192,13 @@ qrng_status check_hash_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const 
   return QRNG_OK;
 }
 
-// Default path choice until a tuned plan table says otherwise: the direct
-// product costs m n / 32 bit-ops, the transform about 40 (n+m) log2(n+m)
-// modular ops; the crossover on MI355X sits near n = 2^15.
-int choose_path(uint64_t n, uint64_t m) {
+// Default path choice: the direct product costs m n / 32 bit-ops, the
+// transform about 40 (n+m) log2(n+m) modular ops; the single-block crossover
+// on MI355X sits near n = 2^15.  Many blocks sharing a seed make the int8
+// matrix-core product the fastest up to n = 3 2^13 (measured: 341 vs 176
+// Gbit/s direct at n = 2^12, 98 vs 50 Gbit/s NTT at n = 2^14).
+int choose_path(uint64_t n, uint64_t m, uint64_t batch = 1) {
+  if (batch >= 32 && n <= 3u * (1u << 13)) return QRNG_PATH_MFMA;
   if (n < (1u << 15)) return QRNG_PATH_DIRECT;
   NttPlan p;
   if (!ntt_make_plan(n, m, &p)) return QRNG_PATH_DIRECT;
@@ -361,6 +365,34 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
 }  // namespace
 
 namespace qrng {
+int ctx_num_cus(const qrng_ctx* c) { return c->num_cus; }
+int ctx_device(const qrng_ctx* c) { return c->device; }
+bool ctx_pin_seed(qrng_ctx* c, uint32_t seed_id, int delta, uint64_t* L) {
+  auto it = c->seeds.find(seed_id);
+  if (it == c->seeds.end()) return false;
+  if (L) *L = it->second.L;
+  if (delta > 0)
+    ++it->second.plans;
+  else if (delta < 0 && it->second.plans)
+    --it->second.plans;
+  return true;
+}
+void ctx_track_server(qrng_ctx* c, qrng_server* s, bool add) {
+  if (add)
+    c->servers.insert(s);
+  else
+    c->servers.erase(s);
+}
+qrng_status set_error(qrng_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
 void prof_begin(int kid, hipStream_t s) {
   qrng_ctx* c = t_ctx;
   if (!c || !c->prof_on) return;
@@ -472,6 +504,7 @@ void qrng_destroy(qrng_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
+  while (!c->servers.empty()) qrng_server_destroy(*c->servers.begin());
   while (!c->plans.empty()) qrng_plan_destroy(*c->plans.begin());
   for (auto& kv : c->seeds)
     for (auto& sp : kv.second.spectra) (void)hipFree(sp.second);
@@ -661,7 +694,7 @@ qrng_status qrng_toeplitz_hash_strided(qrng_ctx* ctx, const uint64_t* x_pool, ui
   DeviceGuard g(ctx->device);
   CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int p = path == QRNG_PATH_AUTO ? choose_path(n, m) : path;
+  const int p = path == QRNG_PATH_AUTO ? choose_path(n, m, nblocks) : path;
   uint64_t cap = nblocks;
   if (p == QRNG_PATH_NTT) {
     NttPlan pl;
@@ -714,7 +747,7 @@ qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
     const uint64_t n = std::get<0>(kv.first), m = std::get<1>(kv.first);
     Seed& sd = ctx->seeds[std::get<2>(kv.first)];
     const std::vector<uint32_t>& ids = kv.second;
-    int p = path == QRNG_PATH_AUTO ? choose_path(n, m) : path;
+    int p = path == QRNG_PATH_AUTO ? choose_path(n, m, ids.size()) : path;
     size_t i = 0;
     while (i < ids.size()) {
       // longest run with constant x and y strides
