@@ -259,6 +259,70 @@ def bench_sweep(ctx, q, torch, qi, reps=3):
     return {"workload": cfg["name"], "unit": "raw Gbit/s", "by_block_bits": res}
 
 
+def bench_serve(ctx, q, torch, qi, seconds=0.6, nwin=4):
+    """Open-loop serving: Poisson arrivals of requests for R bits (R log-uniform
+    in [2^8, 2^24]) at several rates; the serving loop batches whatever has
+    arrived each step.  Latency = completion seen by the host - scheduled
+    arrival.  Windows of 2^24 samples are fed whenever a slot is free (the
+    pre-generated windows are reused in turn)."""
+    import numpy as np
+    cfg = qi.config(4)
+    W = cfg["window_samples"]
+    wins = [torch.from_numpy(qi.gen_adc(W, cfg["sigma"], seed=cfg["adc_seed"] + k)).to("cuda:0")
+            for k in range(nwin)]
+    L = 1 << 19
+    sid = ctx.register_seed(_dev_words(torch, qi.gen_seed_words(L, cfg["seed_seed"])), L)
+    res = {"workload": cfg["name"], "window_samples": W, "rates": {}}
+    try:
+        srv = ctx.server(sid, W, block_bits=0, ring_bits=1 << 31, window_slots=8,
+                         max_queue=1 << 20)
+        res["block_bits"] = srv.stats()["block_bits"]
+        fed = [0]
+
+        def feed_all():
+            while srv.try_feed(wins[fed[0] % nwin]):
+                fed[0] += 1
+
+        for rate in cfg["rates"]:
+            N = max(50, int(rate * seconds))
+            arr = qi.poisson_arrivals(rate, N, cfg["arrival_seed"] + rate)
+            size = qi.request_sizes(N, cfg["r_log2_min"], cfg["r_log2_max"],
+                                    cfg["arrival_seed"] + 7 * rate)
+            due = {}
+            lat = []
+            i = 0
+            feed_all()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while len(lat) < N:
+                now = time.perf_counter() - t0
+                while i < N and arr[i] <= now:
+                    due[srv.submit(int(size[i]))] = arr[i]
+                    i += 1
+                srv.step()
+                got = srv.poll()
+                if got:
+                    tnow = time.perf_counter() - t0
+                    for s in got:
+                        lat.append(tnow - due.pop(s["request_id"]))
+                        if s["status"] == 0:
+                            srv.release(s["request_id"])
+                feed_all()
+            span = time.perf_counter() - t0
+            lat = np.sort(np.array(lat))
+            res["rates"][str(rate)] = {
+                "requests": N, "p50_ms": round(float(lat[N // 2]) * 1e3, 3),
+                "p99_ms": round(float(lat[min(N - 1, int(N * 0.99))]) * 1e3, 3),
+                "served_gbps": round(float(size.sum()) / span / 1e9, 3),
+                "offered_gbps": round(float(size.sum()) / float(arr[-1]) / 1e9, 3)}
+        st = srv.stats()
+        res["windows_fed"] = st["windows_fed"]
+        srv.close()
+    finally:
+        ctx.unregister_seed(sid)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +334,9 @@ def main():
     ap.add_argument("--extras", type=int, default=1, help="also time the other paths")
     ap.add_argument("--uneven", type=int, default=1, help="also time the 4096-block uneven plan")
     ap.add_argument("--sweep", type=int, default=1, help="also time the block-length sweep")
+    ap.add_argument("--serve", type=int, default=1, help="also run the serving-loop latency test")
+    ap.add_argument("--only", choices=["uneven", "sweep", "serve"],
+                    help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -293,6 +360,13 @@ def main():
 
     import paper_2011_04130_amd as q
     import qrng_inputs as qi
+
+    if args.only:
+        ctx = q.Context(0)
+        fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve}[args.only]
+        print(json.dumps(fn(ctx, q, torch, qi)))
+        ctx.close()
+        return
 
     cfg = qi.config(1)
     n, S = cfg["n"], cfg["S"]
@@ -401,6 +475,8 @@ def main():
         out["uneven_4096"] = bench_uneven(ctx, q, torch, qi)
     if args.sweep:
         out["sweep_2^30"] = bench_sweep(ctx, q, torch, qi)
+    if args.serve:
+        out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(xw, n, sw, m, args.cpu_seconds)
     ctx.close()
