@@ -24,7 +24,10 @@
  * Errors: argument errors are detected before anything is enqueued and return
  * QRNG_EINVAL; HIP failures return QRNG_EDEVICE.  The library never aborts.
  * qrng_last_error() gives a thread-local message for the last failure.
- * A context may be used from one host thread at a time.
+ * A context may be used from one host thread at a time, and its workspace
+ * (transform buffers, histogram scratch) is shared by its calls: work that
+ * calls enqueue on different streams must not overlap in time.  Plans and
+ * servers own their workspace.
  */
 #ifndef QRNG_H
 #define QRNG_H

@@ -107,16 +107,12 @@ hipError_t mfma_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bi
                      uint32_t* y_bits, int batch, uint64_t x_stride_bits,
                      uint64_t y_stride_bits, hipStream_t s, const uint64_t* m_dev = nullptr);
 
-// ------------------------------------------------------------- histogram
-hipError_t histogram_u8(const uint8_t* samples, uint64_t S, int nbins,
-                        unsigned long long* counts /* nbins + 1 */, int num_cus,
-                        hipStream_t s);
-
-// Min-entropy finish on the device (one workgroup): model, H_min, d_U,
-// Delta H_m, H_modify from the counts, and m = n H/N - 2 log2(1/eps)
-// (whole bits per sample, clamped to [0, m_cap]).  `out` is a qrng_me_result.
+// ------------------------------------------------------- histogram, estimate
+// Min-entropy finish on the device: model, H_min, d_U, Delta H_m, H_modify
+// from the counts, and m = n H/N - 2 log2(1/eps) (whole bits per sample,
+// clamped to [0, m_cap]).  `out` is a qrng_me_result (nullable), m_out a
+// uint64 (nullable).
 struct MeDevArgs {
-  const unsigned long long* counts;
   int N, model, u_mode;
   double mu, sigma;
   uint64_t n;
@@ -125,7 +121,18 @@ struct MeDevArgs {
   void* out;
   uint64_t* m_out;
 };
-hipError_t minentropy_device(const MeDevArgs& a, hipStream_t s);
+
+constexpr int HIST_MAX_GROUPS = 256;
+// uint32 words of the scratch (partial histograms) one hist_estimate call
+// uses; calls that share it must be ordered on one stream.
+uint64_t hist_scratch_words();
+// Two launches: histogram of S samples of N bits (N <= 8); counts_out
+// (nullable, device) receives the 2^N counts and then the number of samples
+// >= 2^N; with `finish` the estimate and m are written on the device.
+// S < 2^40.
+hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
+                         unsigned long long* counts_out, const MeDevArgs* finish,
+                         hipStream_t s);
 
 // Per-block estimates of an uneven batch of 8-bit sample blocks (one
 // workgroup each): block b's histogram, estimate (out[b], nullable) and

@@ -114,6 +114,7 @@ struct qrng_ctx {
   uint32_t* work = nullptr;  // general workspace
   uint64_t work_words = 0;
   unsigned long long* counts_dev = nullptr;
+  uint32_t* hist_scratch = nullptr;           // partial histograms + ticket (zeroed once)
   unsigned long long* counts_host = nullptr;  // pinned
   qrng_me_result* me_dev = nullptr;           // qrng_extract's default result slot
   uint64_t* m_dev = nullptr;                  // and output-length slot
@@ -484,6 +485,8 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
             hipMalloc(&c->g_lo, 4096 * 4) == hipSuccess &&
             hipMalloc(&c->g_hi, 2048 * 4) == hipSuccess &&
             hipMalloc(&c->counts_dev, 257 * 8) == hipSuccess &&
+            hipMalloc(&c->hist_scratch, hist_scratch_words() * 4) == hipSuccess &&
+            hipMemset(c->hist_scratch, 0, hist_scratch_words() * 4) == hipSuccess &&
             hipMalloc(&c->me_dev, sizeof(qrng_me_result)) == hipSuccess &&
             hipMalloc(&c->m_dev, 8) == hipSuccess &&
             hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
@@ -516,6 +519,7 @@ void qrng_destroy(qrng_ctx* c) {
   if (c->g_hi) (void)hipFree(c->g_hi);
   if (c->work) (void)hipFree(c->work);
   if (c->counts_dev) (void)hipFree(c->counts_dev);
+  if (c->hist_scratch) (void)hipFree(c->hist_scratch);
   if (c->me_dev) (void)hipFree(c->me_dev);
   if (c->m_dev) (void)hipFree(c->m_dev);
   if (c->counts_host) (void)hipHostFree(c->counts_host);
@@ -546,6 +550,7 @@ qrng_status qrng_minentropy(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   const int N = opts->sample_bits;
   if (N < 1 || N > 8) return fail(QRNG_EINVAL, "sample_bits must be 1..8 for byte samples");
   if (S == 0) return fail(QRNG_EINVAL, "no samples");
+  if (S >= (1ull << 40)) return fail(QRNG_EINVAL, "at most 2^40 - 1 samples per call");
   if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
     return fail(QRNG_EINVAL, "unknown model");
   if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
@@ -558,7 +563,7 @@ qrng_status qrng_minentropy(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int K = 1 << N;
-  HIP_TRY(histogram_u8(samples, S, K, ctx->counts_dev, ctx->num_cus, s));
+  HIP_TRY(hist_estimate(samples, S, N, ctx->hist_scratch, ctx->counts_dev, nullptr, s));
   HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (ctx->counts_host[K])
@@ -657,9 +662,7 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint64_t* md = m_dev ? m_dev : ctx->m_dev;
-  HIP_TRY(histogram_u8(samples, S, 256, ctx->counts_dev, ctx->num_cus, s));
   MeDevArgs a{};
-  a.counts = ctx->counts_dev;
   a.N = 8;
   a.model = opts->model;
   a.u_mode = opts->u_mode;
@@ -670,7 +673,7 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   a.m_cap = m_cap;
   a.out = out_dev ? (void*)out_dev : (void*)ctx->me_dev;
   a.m_out = md;
-  HIP_TRY(minentropy_device(a, s));
+  HIP_TRY(hist_estimate(samples, S, 8, ctx->hist_scratch, nullptr, &a, s));
   return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y, path,
                   s, 1, 0, 0, md);
 }

@@ -54,7 +54,7 @@ struct qrng_server {
   qrng_server_cfg cfg{};
   hipStream_t stream = nullptr;
   uint8_t* slots = nullptr;                  // window_slots x W bytes
-  unsigned long long* counts = nullptr;      // per slot 257 counters
+  uint32_t* hist = nullptr;                  // estimate scratch (zeroed once)
   qrng_me_result* me = nullptr;              // per slot
   uint64_t* m_dev = nullptr;                 // per slot
   uint64_t* m_host = nullptr;                // pinned, per slot
@@ -205,7 +205,7 @@ void free_server(qrng_server* s) {
   for (hipEvent_t e : s->events) s->event_pool.push_back(e);
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->slots) (void)hipFree(s->slots);
-  if (s->counts) (void)hipFree(s->counts);
+  if (s->hist) (void)hipFree(s->hist);
   if (s->me) (void)hipFree(s->me);
   if (s->m_dev) (void)hipFree(s->m_dev);
   if (s->m_host) (void)hipHostFree(s->m_host);
@@ -281,7 +281,8 @@ qrng_status qrng_server_create(qrng_ctx* ctx, const qrng_server_cfg* cfg, qrng_s
   const uint32_t K = c.window_slots;
   bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc(&s->slots, (uint64_t)K * c.window_samples) == hipSuccess &&
-            hipMalloc(&s->counts, (uint64_t)K * 257 * 8) == hipSuccess &&
+            hipMalloc(&s->hist, hist_scratch_words() * 4) == hipSuccess &&
+            hipMemset(s->hist, 0, hist_scratch_words() * 4) == hipSuccess &&
             hipMalloc(&s->me, (uint64_t)K * sizeof(qrng_me_result)) == hipSuccess &&
             hipMalloc(&s->m_dev, (uint64_t)K * 8) == hipSuccess &&
             hipHostMalloc(&s->m_host, (uint64_t)K * 8, hipHostMallocDefault) == hipSuccess &&
@@ -335,10 +336,7 @@ qrng_status qrng_server_feed(qrng_server* s, const uint8_t* samples, void* strea
   SRV_HIP(hipStreamWaitEvent(s->stream, copied, 0));
   s->event_pool.push_back(copied);  // reusable once recorded again later; waits are enqueued
   // the window's estimate, with n = n_s: m_s for its blocks
-  unsigned long long* cnt = s->counts + (uint64_t)slot * 257;
-  SRV_HIP(histogram_u8(dst, W, 256, cnt, ctx_num_cus(s->ctx), s->stream));
   MeDevArgs a{};
-  a.counts = cnt;
   a.N = 8;
   a.model = s->cfg.opts.model;
   a.u_mode = s->cfg.opts.u_mode;
@@ -349,7 +347,7 @@ qrng_status qrng_server_feed(qrng_server* s, const uint8_t* samples, void* strea
   a.m_cap = s->cfg.block_bits;
   a.out = s->me + slot;
   a.m_out = s->m_dev + slot;
-  SRV_HIP(minentropy_device(a, s->stream));
+  SRV_HIP(hist_estimate(dst, W, 8, s->hist, nullptr, &a, s->stream));
   SRV_HIP(hipMemcpyAsync(s->m_host + slot, s->m_dev + slot, 8, hipMemcpyDeviceToHost, s->stream));
   Window w;
   w.seq = s->fed++;
