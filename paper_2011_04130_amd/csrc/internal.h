@@ -32,13 +32,16 @@ void prof_end(int kid, hipStream_t s);
 // Per-sub-length twiddle tables (w, floor(w 2^32/p)) and the two-level
 // Montgomery table of the 2^23-rd root used by the four-step twiddles.
 struct TwTables {
-  const uint2* fwd;
+  const uint2* fwd;    // entry (b, a) of a sub-length table at b * r + a
   const uint2* inv;
+  const uint2* fwd_t;  // the same tables transposed: entry (b, a) at a * s + b
+  const uint2* inv_t;
   const uint32_t* g_lo;  // 4096 entries: w^j 2^32 mod p
   const uint32_t* g_hi;  // 2048 entries: w^(4096 j) 2^32 mod p
 };
 
-// Host-built table contents (sizes in entries).
+// Host-built table contents (sizes in entries; fwd and inv hold
+// 2 tw_total_entries(): the tables, then their transposed copies).
 int tw_total_entries();
 void build_tw_tables(uint2* fwd, uint2* inv, uint32_t* g_lo, uint32_t* g_hi);
 

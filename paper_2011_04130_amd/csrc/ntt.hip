@@ -113,7 +113,19 @@ __device__ __forceinline__ void load_tw(const uint2* __restrict__ T, uint2 (&t)[
 // hides load latency.  Forward: radix-r DIF then twiddle w_R^(b bitrev(a'));
 // inverse: twiddle w_R^-(b bitrev(a')) then radix-r DIT.
 // ld(g, a) / st(g, a, v) address element a of group g.
-template <int LOG, int k, int GPT, bool INV, class LD, class ST>
+// TP: the tables in transposed order (entry (b, a) at a * s + b), so lanes
+// that hold consecutive groups b read consecutive entries.
+template <int R, int S, bool TP>
+__device__ __forceinline__ void group_tw(const uint2* __restrict__ T, int b, uint2 (&t)[R]) {
+  if constexpr (TP) {
+#pragma unroll
+    for (int a = 1; a < R; ++a) t[a] = T[a * S + b];
+  } else {
+    load_tw<R>(T + b * R, t);
+  }
+}
+
+template <int LOG, int k, int GPT, bool INV, bool TP, class LD, class ST>
 __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __restrict__ tws,
                                             LD&& ld, ST&& st) {
   using G = Geo<LOG, k>;
@@ -127,7 +139,7 @@ __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __re
     if constexpr (INV) {
       if constexpr (G::s > 1) {
         uint2 t[G::r];
-        load_tw<G::r>(tws + G::toff + ((g0 + u * gstep) % G::s) * G::r, t);
+        group_tw<G::r, G::s, TP>(tws + G::toff, (g0 + u * gstep) % G::s, t);
 #pragma unroll
         for (int a = 1; a < G::r; ++a) v[u][a] = mul_shoup(v[u][a], t[a].x, t[a].y);
       }
@@ -136,7 +148,7 @@ __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __re
       dft_reg<G::r, false>(v[u]);
       if constexpr (G::s > 1) {
         uint2 t[G::r];
-        load_tw<G::r>(tws + G::toff + ((g0 + u * gstep) % G::s) * G::r, t);
+        group_tw<G::r, G::s, TP>(tws + G::toff, (g0 + u * gstep) % G::s, t);
 #pragma unroll
         for (int a = 1; a < G::r; ++a) v[u][a] = mul_shoup(v[u][a], t[a].x, t[a].y);
       }
@@ -150,7 +162,7 @@ __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __re
 
 // Every group of round k, NT threads (this thread = t), at most GMAX groups
 // in flight per thread.
-template <int LOG, int k, int NT, int GMAX, bool INV, class LD, class ST>
+template <int LOG, int k, int NT, int GMAX, bool INV, bool TP = false, class LD, class ST>
 __device__ __forceinline__ void round_all(int t, const uint2* __restrict__ tws, LD&& ld, ST&& st) {
   constexpr int groups = Geo<LOG, k>::groups;
   if constexpr (groups >= NT) {
@@ -158,9 +170,9 @@ __device__ __forceinline__ void round_all(int t, const uint2* __restrict__ tws, 
     constexpr int gpt = per < GMAX ? per : GMAX;
 #pragma unroll 1
     for (int it = 0; it < per / gpt; ++it)
-      round_multi<LOG, k, gpt, INV>(t + it * gpt * NT, NT, tws, ld, st);
+      round_multi<LOG, k, gpt, INV, TP>(t + it * gpt * NT, NT, tws, ld, st);
   } else {
-    if (t < groups) round_multi<LOG, k, 1, INV>(t, NT, tws, ld, st);
+    if (t < groups) round_multi<LOG, k, 1, INV, TP>(t, NT, tws, ld, st);
   }
 }
 
@@ -459,6 +471,11 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   const int zy = blockIdx.y;
   const int32_t Nc = 1 << a.log_nc;
   const NttItem* desc = SEED ? nullptr : (a.items ? a.items + zy : nullptr);
+  // transposed twiddle tables (lane-contiguous loads) pay off up to 2^13-point
+  // rows; at 2^14 the per-group layout measured faster
+  constexpr bool TPT = LOG2 < 14;
+  const uint2* twf = TPT ? tw.fwd_t : tw.fwd;
+  const uint2* twi = TPT ? tw.inv_t : tw.inv;
 
   auto ld_lds_k = [&](auto kc) {
     return [&](int g, int e) -> uint32_t {
@@ -493,16 +510,16 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
         const int q = G0::pos0(g) + e * G0::s;
         return (wbits[q >> 5] >> (q & 31)) & 1u;
       };
-      round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
+      round_all<LOG2, 0, T, GPT, false, TPT>(tid, twf, ld0, st_lds_k(k0));
     } else {
       // no __restrict__: with one transform pass B works in place (in == out)
       const uint32_t* src = a.in + (uint64_t)item * (uint32_t)Nc + (uint64_t)row * N2;
       auto ld0 = [&](int g, int e) -> uint32_t { return src[G0::pos0(g) + e * G0::s]; };
-      round_all<LOG2, 0, T, GPT, false>(tid, tw.fwd, ld0, st_lds_k(k0));
+      round_all<LOG2, 0, T, GPT, false, TPT>(tid, twf, ld0, st_lds_k(k0));
     }
     __syncthreads();
     static_for<1, K - 1>([&](auto kc) {
-      round_all<LOG2, decltype(kc)::value, T, GPT, false>(tid, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
+      round_all<LOG2, decltype(kc)::value, T, GPT, false, TPT>(tid, twf, ld_lds_k(kc), st_lds_k(kc));
       __syncthreads();
     });
 #pragma unroll
@@ -517,9 +534,12 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   });
 
   if constexpr (SEED) {
+    // spectrum row layout: element e of last-round group g at
+    // (e / 4) * N2/4 + 4 g + e % 4, so the hash's 16-byte loads of
+    // consecutive groups (lanes) are consecutive
 #pragma unroll
     for (int u = 0; u < GPT; ++u) {
-      uint32_t* dst = a.out + (uint64_t)zy * (uint32_t)Nc + (uint64_t)row * N2 + (tid + u * T) * 16;
+      uint32_t* dst = a.out + (uint64_t)zy * (uint32_t)Nc + (uint64_t)row * N2 + (tid + u * T) * 4;
 #pragma unroll
       for (int e = 0; e < 16; e += 4) {
         uint4 w;
@@ -527,7 +547,7 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
         w.y = red1(mul_mont(xs[0][u][e + 1], a.cw));
         w.z = red1(mul_mont(xs[0][u][e + 2], a.cw));
         w.w = red1(mul_mont(xs[0][u][e + 3], a.cw));
-        *reinterpret_cast<uint4*>(dst + e) = w;
+        *reinterpret_cast<uint4*>(dst + (e / 4) * (N2 / 4)) = w;
       }
     }
     return;
@@ -544,10 +564,10 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
                              (uint64_t)row * N2;
 #pragma unroll
         for (int u = 0; u < GPT; ++u) {
-          const uint32_t* wg = wr + (tid + u * T) * 16;
+          const uint32_t* wg = wr + (tid + u * T) * 4;
 #pragma unroll
           for (int e = 0; e < 16; e += 4) {
-            const uint4 w = *reinterpret_cast<const uint4*>(wg + e);
+            const uint4 w = *reinterpret_cast<const uint4*>(wg + (e / 4) * (N2 / 4));
             acc[u][e + 0] = red2(acc[u][e + 0] + mul_mont(xs[c][u][e + 0], w.x));
             acc[u][e + 1] = red2(acc[u][e + 1] + mul_mont(xs[c][u][e + 1], w.y));
             acc[u][e + 2] = red2(acc[u][e + 2] + mul_mont(xs[c][u][e + 2], w.z));
@@ -564,7 +584,7 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
       }
       __syncthreads();
       static_for_down<1, K - 1>([&](auto kc) {
-        round_all<LOG2, decltype(kc)::value, T, GPT, true>(tid, tw.inv, ld_lds_k(kc), st_lds_k(kc));
+        round_all<LOG2, decltype(kc)::value, T, GPT, true, TPT>(tid, twi, ld_lds_k(kc), st_lds_k(kc));
         __syncthreads();
       });
       if constexpr (OUT_BITS) {
@@ -582,12 +602,12 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
           const int q0 = q - lane;
           if (lane == 0 && q0 < ylimit) y64[q0 >> 6] = bal;
         };
-        round_all<LOG2, 0, T, GPT, true>(tid, tw.inv, ld_lds_k(k0), st_bits);
+        round_all<LOG2, 0, T, GPT, true, TPT>(tid, twi, ld_lds_k(k0), st_bits);
       } else {
         uint32_t* __restrict__ dst =
             a.out + (uint64_t)(zy * a.ny + o) * (uint32_t)Nc + (uint64_t)row * N2;
         auto st0 = [&](int g, int e, uint32_t v) { dst[G0::pos0(g) + e * G0::s] = v; };
-        round_all<LOG2, 0, T, GPT, true>(tid, tw.inv, ld_lds_k(k0), st0);
+        round_all<LOG2, 0, T, GPT, true, TPT>(tid, twi, ld_lds_k(k0), st0);
       }
       __syncthreads();
     }
@@ -712,6 +732,9 @@ void build_tw_tables(uint2* fwd, uint2* inv, uint32_t* g_lo, uint32_t* g_hi) {
           const uint32_t f = host_pow(w, e), g = host_pow(iw, e);
           fwd[off + b * r + ap] = make_uint2(f, shoup_q(f));
           inv[off + b * r + ap] = make_uint2(g, shoup_q(g));
+          // transposed copy
+          fwd[TW_TOTAL + off + ap * s + b] = make_uint2(f, shoup_q(f));
+          inv[TW_TOTAL + off + ap * s + b] = make_uint2(g, shoup_q(g));
         }
     }
   }

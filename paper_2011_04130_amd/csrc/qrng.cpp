@@ -477,11 +477,11 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
   const int T = tw_total_entries();
-  std::vector<uint2> f(T), iv(T);
+  std::vector<uint2> f(2 * T), iv(2 * T);
   std::vector<uint32_t> lo(4096), hi(2048);
   build_tw_tables(f.data(), iv.data(), lo.data(), hi.data());
-  bool ok = hipMalloc(&c->tw_fwd, T * sizeof(uint2)) == hipSuccess &&
-            hipMalloc(&c->tw_inv, T * sizeof(uint2)) == hipSuccess &&
+  bool ok = hipMalloc(&c->tw_fwd, 2 * T * sizeof(uint2)) == hipSuccess &&
+            hipMalloc(&c->tw_inv, 2 * T * sizeof(uint2)) == hipSuccess &&
             hipMalloc(&c->g_lo, 4096 * 4) == hipSuccess &&
             hipMalloc(&c->g_hi, 2048 * 4) == hipSuccess &&
             hipMalloc(&c->counts_dev, 257 * 8) == hipSuccess &&
@@ -490,15 +490,15 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
             hipMalloc(&c->me_dev, sizeof(qrng_me_result)) == hipSuccess &&
             hipMalloc(&c->m_dev, 8) == hipSuccess &&
             hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipMemcpy(c->tw_fwd, f.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
-  ok = ok && hipMemcpy(c->tw_inv, iv.data(), T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(c->tw_fwd, f.data(), 2 * T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(c->tw_inv, iv.data(), 2 * T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(c->g_lo, lo.data(), 4096 * 4, hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(c->g_hi, hi.data(), 2048 * 4, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     qrng_destroy(c);
     return fail(QRNG_EDEVICE, "context setup on device %d failed", device);
   }
-  c->tw = TwTables{c->tw_fwd, c->tw_inv, c->g_lo, c->g_hi};
+  c->tw = TwTables{c->tw_fwd, c->tw_inv, c->tw_fwd + T, c->tw_inv + T, c->g_lo, c->g_hi};
   *out = c;
   return QRNG_OK;
 }
