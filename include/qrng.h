@@ -325,6 +325,13 @@ qrng_status qrng_server_feed(qrng_server *srv, const uint8_t *samples_dev, void 
  * QRNG_EBUSY if max_queue requests are already waiting. */
 qrng_status qrng_server_submit(qrng_server *srv, uint64_t bits, uint64_t *request_id);
 
+/* Queue up to `count` requests in order (bits_host[i] > 0 each, else
+ * QRNG_EINVAL and none queued).  Requests 0 .. *accepted - 1 are queued
+ * (acceptance stops at the first that would exceed max_queue) and
+ * ids_host[i] receives the id of request i. */
+qrng_status qrng_server_submit_many(qrng_server *srv, const uint64_t *bits_host, uint32_t count,
+                                    uint64_t *ids_host, uint32_t *accepted);
+
 /* Admit what fits and enqueue the hashes (never waits for the GPU except
  * for the estimate of a window it moves to).  *admitted (nullable) receives
  * the number of requests admitted. */
@@ -338,9 +345,14 @@ qrng_status qrng_server_poll(qrng_server *srv, qrng_served *out_host, uint32_t c
 /* Give a completed request's ring space back. */
 qrng_status qrng_server_release(qrng_server *srv, uint64_t request_id);
 
+/* Release many: ids that hold no ring space or are not completed are
+ * skipped. */
+qrng_status qrng_server_release_many(qrng_server *srv, const uint64_t *ids_host, uint32_t count);
+
 /* Copy a completed request's R output bits (ceil(R/64) words, bits past R
  * written as 0) to out_dev, enqueued on `stream`.  The ring space stays held
- * until qrng_server_release. */
+ * until qrng_server_release, which must come after the copy has run (the
+ * server's later hashes may reuse the space at once). */
 qrng_status qrng_server_read(qrng_server *srv, uint64_t request_id, uint64_t *out_dev,
                              void *stream);
 

@@ -91,7 +91,8 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
            "qrng_plan_create", "qrng_plan_execute", "qrng_plan_query", "qrng_plan_destroy",
            "qrng_tune_export", "qrng_tune_import",
-           "qrng_server_create", "qrng_server_feed", "qrng_server_submit", "qrng_server_step",
+           "qrng_server_create", "qrng_server_feed", "qrng_server_submit",
+           "qrng_server_submit_many", "qrng_server_release_many", "qrng_server_step",
            "qrng_server_poll", "qrng_server_release", "qrng_server_read", "qrng_server_ring",
            "qrng_server_window",
            "qrng_server_query", "qrng_server_destroy",
@@ -156,14 +157,16 @@ def load_library(path: str | None = None):
     lib.qrng_server_feed.argtypes = [vp, vp, vp]
     lib.qrng_server_submit.argtypes = [vp, u64, ctypes.POINTER(u64)]
     lib.qrng_server_step.argtypes = [vp, ctypes.POINTER(u32)]
+    lib.qrng_server_submit_many.argtypes = [vp, vp, u32, vp, ctypes.POINTER(u32)]
+    lib.qrng_server_release_many.argtypes = [vp, vp, u32]
     lib.qrng_server_poll.argtypes = [vp, ctypes.POINTER(Served), u32, ctypes.POINTER(u32)]
     lib.qrng_server_release.argtypes = [vp, u64]
     lib.qrng_server_read.argtypes = [vp, u64, vp, vp]
     lib.qrng_server_ring.argtypes = [vp, ctypes.POINTER(vp)]
     lib.qrng_server_window.argtypes = [vp, u64, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.qrng_server_query.argtypes = [vp, ctypes.POINTER(ServerStats)]
-    for f in ("create", "feed", "submit", "step", "poll", "release", "read", "ring", "window",
-              "query"):
+    for f in ("create", "feed", "submit", "submit_many", "step", "poll", "release",
+              "release_many", "read", "ring", "window", "query"):
         getattr(lib, "qrng_server_" + f).restype = i32
     lib.qrng_server_destroy.argtypes = [vp]
     lib.qrng_server_destroy.restype = None

@@ -347,18 +347,47 @@ class Server:
 
     def try_feed(self, samples, stream=None) -> bool:
         """feed(), but False instead of an error when every slot is busy."""
-        try:
-            self.feed(samples, stream)
-            return True
-        except QrngError as e:
-            if e.status == -5:
-                return False
-            raise
+        torch = self._ctx._torch
+        p = self._ctx._dev_tensor(samples, "samples", torch.uint8)
+        st = self._lib.qrng_server_feed(self._h, p, _stream(torch, self._ctx.device, stream))
+        if st == -5:
+            return False
+        check(st)
+        return True
 
     def submit(self, bits: int) -> int:
         rid = ctypes.c_uint64()
         check(self._lib.qrng_server_submit(self._h, bits, ctypes.byref(rid)))
         return rid.value
+
+    def submit_many(self, bits):
+        """Queue many requests (numpy-convertible sizes); returns the
+        accepted ids as a uint64 array (shorter if the queue filled)."""
+        import numpy as np
+        b = np.ascontiguousarray(np.asarray(bits, dtype=np.uint64))
+        ids = np.empty(len(b), dtype=np.uint64)
+        n = ctypes.c_uint32()
+        check(self._lib.qrng_server_submit_many(self._h, b.ctypes.data, len(b), ids.ctypes.data,
+                                                ctypes.byref(n)))
+        return ids[: n.value]
+
+    def release_many(self, ids) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+        check(self._lib.qrng_server_release_many(self._h, a.ctypes.data, len(a)))
+
+    def poll_array(self, cap: int = 1 << 16):
+        """Completed requests as a numpy structured array (fields of qrng_served)."""
+        import numpy as np
+        dt = np.dtype([("request_id", "<u8"), ("bits", "<u8"), ("ring_word", "<u8"),
+                       ("window", "<u8"), ("first_block", "<u8"), ("blocks", "<u4"),
+                       ("status", "<i4"), ("m_block", "<u8")])
+        assert dt.itemsize == ctypes.sizeof(Served)
+        out = np.empty(cap, dtype=dt)
+        n = ctypes.c_uint32()
+        check(self._lib.qrng_server_poll(self._h, out.ctypes.data_as(ctypes.POINTER(Served)), cap,
+                                         ctypes.byref(n)))
+        return out[: n.value]
 
     def step(self) -> int:
         n = ctypes.c_uint32()

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <deque>
 #include <map>
+#include <unordered_set>
 #include <vector>
 
 #include "internal.h"
@@ -49,10 +50,17 @@ struct Region {
 
 }  // namespace
 
+// Hash launches allowed in flight: one running and one queued behind it.
+// While both are busy, admitted requests wait and join a later, larger run
+// (continuous batching without a launch per host step).
+constexpr size_t kMaxRunsInFlight = 2;
+
 struct qrng_server {
   qrng_ctx* ctx = nullptr;
   qrng_server_cfg cfg{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;              // hashes
+  hipStream_t est_stream = nullptr;          // window copies and estimates (never
+                                             // queued behind hashes)
   uint8_t* slots = nullptr;                  // window_slots x W bytes
   uint32_t* hist = nullptr;                  // estimate scratch (zeroed once)
   qrng_me_result* me = nullptr;              // per slot
@@ -68,7 +76,9 @@ struct qrng_server {
   std::vector<bool> slot_busy;
   std::deque<Request> queue;
   std::deque<Admitted> inflight;
+  std::unordered_set<uint64_t> inflight_ids;  // admitted, not yet returned by poll
   std::deque<hipEvent_t> events;             // events of launch runs still referenced
+  std::deque<hipEvent_t> runs;               // end events of launches that may still run
   std::vector<hipEvent_t> event_pool;
   uint64_t next_id = 1, fed = 0, used = 0, blocks_hashed = 0, bits_served = 0;
   uint64_t nblk = 0;                         // blocks per window
@@ -159,6 +169,7 @@ qrng_status launch_run(qrng_server* s, const Window& w, uint64_t b0, uint64_t nb
   if (!e) return err(QRNG_EDEVICE, "event creation failed");
   SRV_HIP(hipEventRecord(e, s->stream));
   s->events.push_back(e);
+  s->runs.push_back(e);
   *done = e;
   s->blocks_hashed += nb;
   return QRNG_OK;
@@ -200,6 +211,7 @@ qrng_status time_block_length(qrng_server* s, uint64_t n, double* rate) {
 
 void free_server(qrng_server* s) {
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->est_stream) (void)hipStreamSynchronize(s->est_stream);
   for (auto& w : s->windows)
     if (w.est) s->event_pool.push_back(w.est);
   for (hipEvent_t e : s->events) s->event_pool.push_back(e);
@@ -211,6 +223,7 @@ void free_server(qrng_server* s) {
   if (s->m_host) (void)hipHostFree(s->m_host);
   if (s->ring) (void)hipFree(s->ring);
   if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->est_stream) (void)hipStreamDestroy(s->est_stream);
   ctx_pin_seed(s->ctx, s->cfg.seed_id, -1, nullptr);
   ctx_track_server(s->ctx, s, false);
   delete s;
@@ -280,6 +293,7 @@ qrng_status qrng_server_create(qrng_ctx* ctx, const qrng_server_cfg* cfg, qrng_s
   ctx_track_server(ctx, s, true);
   const uint32_t K = c.window_slots;
   bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipStreamCreateWithFlags(&s->est_stream, hipStreamNonBlocking) == hipSuccess &&
             hipMalloc(&s->slots, (uint64_t)K * c.window_samples) == hipSuccess &&
             hipMalloc(&s->hist, hist_scratch_words() * 4) == hipSuccess &&
             hipMemset(s->hist, 0, hist_scratch_words() * 4) == hipSuccess &&
@@ -315,6 +329,25 @@ qrng_status qrng_server_create(qrng_ctx* ctx, const qrng_server_cfg* cfg, qrng_s
     s->cfg.block_bits = pick;
   }
   s->nblk = c.window_samples * 8 / s->cfg.block_bits;
+  {
+    // load the kernels of both run sizes now (a first launch loads its code
+    // object and would stall the first requests): one block, then 64
+    const uint64_t n = s->cfg.block_bits;
+    for (uint32_t nb : {1u, 64u}) {
+      if (nb > s->nblk || nb * (n / 128) > s->ring_words) continue;
+      qrng_status st = qrng_toeplitz_hash_strided(ctx, reinterpret_cast<const uint64_t*>(s->slots),
+                                                  n, n / 64, c.seed_id, n / 2, s->ring, n / 128,
+                                                  nb, s->cfg.path, s->stream);
+      if (st) {
+        free_server(s);
+        return st;
+      }
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+      free_server(s);
+      return err(QRNG_EDEVICE, "server warm-up failed");
+    }
+  }
   *out = s;
   return QRNG_OK;
 }
@@ -333,7 +366,7 @@ qrng_status qrng_server_feed(qrng_server* s, const uint8_t* samples, void* strea
   hipEvent_t copied = get_event(s);
   if (!copied) return err(QRNG_EDEVICE, "event creation failed");
   SRV_HIP(hipEventRecord(copied, cs));
-  SRV_HIP(hipStreamWaitEvent(s->stream, copied, 0));
+  SRV_HIP(hipStreamWaitEvent(s->est_stream, copied, 0));
   s->event_pool.push_back(copied);  // reusable once recorded again later; waits are enqueued
   // the window's estimate, with n = n_s: m_s for its blocks
   MeDevArgs a{};
@@ -347,14 +380,17 @@ qrng_status qrng_server_feed(qrng_server* s, const uint8_t* samples, void* strea
   a.m_cap = s->cfg.block_bits;
   a.out = s->me + slot;
   a.m_out = s->m_dev + slot;
-  SRV_HIP(hist_estimate(dst, W, 8, s->hist, nullptr, &a, s->stream));
-  SRV_HIP(hipMemcpyAsync(s->m_host + slot, s->m_dev + slot, 8, hipMemcpyDeviceToHost, s->stream));
+  SRV_HIP(hist_estimate(dst, W, 8, s->hist, nullptr, &a, s->est_stream));
+  SRV_HIP(hipMemcpyAsync(s->m_host + slot, s->m_dev + slot, 8, hipMemcpyDeviceToHost,
+                         s->est_stream));
   Window w;
   w.seq = s->fed++;
   w.slot = slot;
   w.est = get_event(s);
   if (!w.est) return err(QRNG_EDEVICE, "event creation failed");
-  SRV_HIP(hipEventRecord(w.est, s->stream));
+  // hashes of this window start only after the host has waited for this
+  // event (window_known), which orders them after the copy
+  SRV_HIP(hipEventRecord(w.est, s->est_stream));
   s->slot_busy[slot] = true;
   s->windows.push_back(w);
   return QRNG_OK;
@@ -369,11 +405,45 @@ qrng_status qrng_server_submit(qrng_server* s, uint64_t bits, uint64_t* id) {
   return QRNG_OK;
 }
 
+qrng_status qrng_server_submit_many(qrng_server* s, const uint64_t* bits, uint32_t count,
+                                    uint64_t* ids, uint32_t* accepted) {
+  if (!s || (count && (!bits || !ids)) || !accepted) return err(QRNG_EINVAL, "null argument");
+  for (uint32_t i = 0; i < count; ++i)
+    if (bits[i] == 0) return err(QRNG_EINVAL, "a request needs at least one bit");
+  uint32_t k = 0;
+  while (k < count && s->queue.size() < s->cfg.max_queue) {
+    ids[k] = s->next_id++;
+    s->queue.push_back(Request{ids[k], bits[k]});
+    ++k;
+  }
+  *accepted = k;
+  return QRNG_OK;
+}
+
+qrng_status qrng_server_release_many(qrng_server* s, const uint64_t* ids, uint32_t count) {
+  if (!s || (count && !ids)) return err(QRNG_EINVAL, "null argument");
+  for (uint32_t i = 0; i < count; ++i) {
+    auto it = s->region_of.find(ids[i]);
+    if (it == s->region_of.end() || s->inflight_ids.count(ids[i])) continue;
+    auto r = s->regions.find(it->second);
+    if (r != s->regions.end()) r->second.released = true;
+    s->region_of.erase(it);
+    s->served_bits.erase(ids[i]);
+  }
+  ring_reclaim(s);
+  return QRNG_OK;
+}
+
 qrng_status qrng_server_step(qrng_server* s, uint32_t* admitted) {
   if (!s) return err(QRNG_EINVAL, "null server");
   Dev g(ctx_device(s->ctx));
   uint32_t adm = 0;
   retire_windows(s);
+  while (!s->runs.empty() && hipEventQuery(s->runs.front()) == hipSuccess) s->runs.pop_front();
+  if (s->runs.size() >= kMaxRunsInFlight) {
+    if (admitted) *admitted = 0;
+    return QRNG_OK;
+  }
   // the current window is the oldest one with blocks left
   size_t wi = 0;
   while (!s->queue.empty() && wi < s->windows.size()) {
@@ -436,6 +506,7 @@ qrng_status qrng_server_step(qrng_server* s, uint32_t* admitted) {
       q.m_block = w.m_s;
       s->region_of[r.id] = start;
       s->served_bits[r.id] = r.bits;
+      s->inflight_ids.insert(r.id);
       run.push_back(q);
       run_blocks += k;
       w.cursor += k;
@@ -474,14 +545,21 @@ qrng_status qrng_server_poll(qrng_server* s, qrng_served* out, uint32_t cap, uin
     }
     out[k++] = a.info;
     if (a.info.status == QRNG_OK) s->bits_served += a.info.bits;
+    s->inflight_ids.erase(a.info.request_id);
     s->inflight.pop_front();
   }
-  // events no completed-or-pending request refers to go back to the pool
+  // events go back to the pool once no request or window refers to them;
+  // events and the requests' references are both in launch order, so only
+  // the oldest referenced event needs looking up
+  hipEvent_t first_ref = nullptr;
+  for (auto& a : s->inflight)
+    if (a.done) {
+      first_ref = a.done;
+      break;
+    }
   while (!s->events.empty()) {
     const hipEvent_t e = s->events.front();
-    bool ref = false;
-    for (auto& a : s->inflight)
-      if (a.done == e) ref = true;
+    bool ref = e == first_ref || (!s->runs.empty() && e == s->runs.front());
     for (auto& w : s->windows)
       if (w.last == e) ref = true;
     if (ref) break;
@@ -497,8 +575,7 @@ qrng_status qrng_server_release(qrng_server* s, uint64_t id) {
   if (!s) return err(QRNG_EINVAL, "null server");
   auto it = s->region_of.find(id);
   if (it == s->region_of.end()) return err(QRNG_EINVAL, "no ring space held by this request");
-  for (auto& a : s->inflight)
-    if (a.info.request_id == id) return err(QRNG_EBUSY, "request not completed yet");
+  if (s->inflight_ids.count(id)) return err(QRNG_EBUSY, "request not completed yet");
   auto r = s->regions.find(it->second);
   if (r != s->regions.end()) r->second.released = true;
   s->region_of.erase(it);
@@ -512,8 +589,7 @@ qrng_status qrng_server_read(qrng_server* s, uint64_t id, uint64_t* out, void* s
   if ((reinterpret_cast<uintptr_t>(out) & 7u) != 0) return err(QRNG_EINVAL, "output must be 8-byte aligned");
   auto it = s->region_of.find(id);
   if (it == s->region_of.end()) return err(QRNG_EINVAL, "no ring space held by this request");
-  for (auto& a : s->inflight)
-    if (a.info.request_id == id) return err(QRNG_EBUSY, "request not completed yet");
+  if (s->inflight_ids.count(id)) return err(QRNG_EBUSY, "request not completed yet");
   auto r = s->regions.find(it->second);
   if (r == s->regions.end()) return err(QRNG_EINVAL, "request region missing");
   // the request's bits: R of the words it holds

@@ -231,3 +231,30 @@ def test_server_config_and_feed_errors(torch, ctx, windows, seed):
             srv.submit(0)
         with pytest.raises(q.QrngError):
             ctx.unregister_seed(sid)          # pinned by the live server
+
+
+def test_server_vector_calls(torch, ctx, windows, seed):
+    """submit_many / poll_array / release_many serve the same bits as the
+    one-at-a-time calls."""
+    sid, sw = seed
+    sizes = [5000, 12, 30000, 2560, 777]
+    with ctx.server(sid, W, block_bits=NS, ring_bits=1 << 22, window_slots=3) as srv:
+        ids = srv.submit_many(sizes)
+        assert list(ids) == sorted(ids) and len(ids) == len(sizes)
+        srv.feed(torch.from_numpy(windows[0]).to("cuda:0"))
+        done = {}
+        for _ in range(1000):
+            srv.step()
+            got = srv.poll_array()
+            for r in got:
+                s = {k: int(r[k]) for k in got.dtype.names}
+                done[s["request_id"]] = (s, srv.read(s["request_id"], s["bits"]).cpu().numpy()
+                                         .view(np.uint64))
+            srv.release_many(got["request_id"])
+            torch.cuda.synchronize()
+            if len(done) == len(sizes):
+                break
+        assert srv.stats()["ring_free_bits"] == 1 << 22
+    for rid in ids:
+        s, w = done[int(rid)]
+        assert np.array_equal(w, want_bits(windows, sw, s, NS))
