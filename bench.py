@@ -35,6 +35,7 @@ P_NTT = 998244353
 PEAK_INT32_MUL = 39.3e12     # 256 CU x 64 lanes/clk x 2.4 GHz, full-rate v_mul_lo/hi_u32
 PEAK_BITOP = 78.6e12         # 2 x the above: simple 32-bit logic ops dual-issue (cf. fp32 157.3 TFLOP/s)
 PEAK_HBM = 8.0e12
+PEAK_INT8 = 5.0e15           # dense int8 MFMA
 
 
 def log2i(v):
@@ -255,6 +256,12 @@ def bench_sweep(ctx, q, torch, qi, reps=3):
             t = _time_fn(torch, lambda: ctx.hash_strided(x, n, n // 64, sid, m, y, yw, B,
                                                           path=path), reps)
             row[name] = round(tot / t / 1e9, 2)
+            if name == "mfma":
+                # the dense int8 product: 2 m n operations per block
+                pops = 2.0 * m * n * B / t / 1e15
+                row["mfma_roofline"] = {"bound": "mfma", "achieved": round(pops, 3),
+                                        "peak": PEAK_INT8 / 1e15, "unit": "POP/s int8",
+                                        "frac": round(pops * 1e15 / PEAK_INT8, 4)}
         ctx.unregister_seed(sid)
         res["2^%d" % lg] = row
     return {"workload": cfg["name"], "unit": "raw Gbit/s", "by_block_bits": res}
