@@ -496,11 +496,33 @@ def main():
             "ntt_registered_seed": round(n / t_seeded / 1e9, 3),
             "ntt_seed_transformed_each_call": round(n / t_plain / 1e9, 3),
             "direct": round(n / t_direct / 1e9, 4)}
+        # the direct product on the same block: m n GF(2) MACs, 32 per bit op
+        bitops = m * n / 32.0 / t_direct
+        out["direct_roofline"] = {"bound": "alu", "achieved": round(bitops / 1e12, 3),
+                                  "peak": PEAK_BITOP / 1e12, "unit": "T bitop/s",
+                                  "frac": round(bitops / PEAK_BITOP, 4),
+                                  "note": "whole call (reversal + product), n = 2^23 block"}
 
+    # HBM rate of each NTT pass from the committed counter summary (null when
+    # the kernels changed since it was taken)
+    hbm = {}
+    for k in ("ntt_cols_fwd", "ntt_rows_hash", "ntt_cols_inv"):
+        b = measured_traffic(k, cfg["name"])
+        if b and k in prof:
+            c_, ms_ = prof[k]
+            gbs = b / (ms_ / c_ / 1e3) / 1e9
+            hbm[k] = {"GB/s": round(gbs, 1), "frac_of_8TB/s": round(gbs * 1e9 / PEAK_HBM, 4),
+                      "bytes_per_launch": b}
+    out["ntt_hbm"] = hbm or None
+    plain = value
     if args.uneven:
         out["uneven_4096"] = bench_uneven(ctx, q, torch, qi)
+        out["uneven_4096"]["raw_vs_plain"] = round(out["uneven_4096"]["raw_gbps"] / plain, 3)
     if args.sweep:
         out["sweep_2^30"] = bench_sweep(ctx, q, torch, qi)
+        out["sweep_2^30"]["best_raw_vs_plain"] = {
+            k: round(max(v for kk, v in row.items() if isinstance(v, float)) / plain, 3)
+            for k, row in out["sweep_2^30"]["by_block_bits"].items()}
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:
