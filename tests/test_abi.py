@@ -94,3 +94,67 @@ def test_create_without_gpu_reports_device_error(lib):
     h = ctypes.c_void_p()
     st = lib.qrng_create(ctypes.byref(h), 0)
     assert st in (-3, -1) and not h.value
+
+
+def test_new_entry_points_reject_null_handles(lib):
+    """Plans, tuning table and server calls fail cleanly without a context
+    or handle (no device work is attempted)."""
+    from paper_2011_04130_amd._lib import Block, MeOpts, PlanInfo, Served, ServerCfg, ServerStats
+    buf = (ctypes.c_uint64 * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    blk = (Block * 1)()
+    assert lib.qrng_plan_create(None, blk, 1, p, p, None, None, None, 0.0, 0, 0, None,
+                                ctypes.byref(h)) == -1 and not h.value
+    assert lib.qrng_plan_create(None, blk, 1, p, p, None, None, None, 0.0, 0, 0, None,
+                                None) == -1
+    assert lib.qrng_plan_execute(None, None) == -1
+    assert lib.qrng_plan_query(None, ctypes.byref(PlanInfo())) == -1
+    lib.qrng_plan_destroy(None)  # no-op
+    n = ctypes.c_uint64()
+    assert lib.qrng_tune_export(None, None, 0, ctypes.byref(n)) == -1
+    assert lib.qrng_tune_import(None, b"ntt 20 10 27\n") == -1
+    cfg = ServerCfg()
+    assert lib.qrng_server_create(None, ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert lib.qrng_server_create(None, ctypes.byref(cfg), None) == -1
+    rid = ctypes.c_uint64()
+    cnt = ctypes.c_uint32()
+    assert lib.qrng_server_submit(None, 10, ctypes.byref(rid)) == -1
+    assert lib.qrng_server_submit_many(None, p, 1, p, ctypes.byref(cnt)) == -1
+    assert lib.qrng_server_step(None, None) == -1
+    assert lib.qrng_server_poll(None, (Served * 1)(), 1, ctypes.byref(cnt)) == -1
+    assert lib.qrng_server_release(None, 1) == -1
+    assert lib.qrng_server_release_many(None, p, 1) == -1
+    assert lib.qrng_server_read(None, 1, p, None) == -1
+    assert lib.qrng_server_query(None, ctypes.byref(ServerStats())) == -1
+    assert lib.qrng_server_feed(None, p, None) == -1
+    lib.qrng_server_destroy(None)  # no-op
+    assert lib.qrng_extract(None, p, 8, ctypes.byref(MeOpts(8, 0, 0.0, 0.0, 0, 0)), 0.0, 1, 8,
+                            p, None, None, 0, None) == -1
+    assert lib.qrng_toeplitz_hash_strided(None, p, 64, 1, 1, 32, p, 1, 1, 0, None) == -1
+
+
+def test_struct_layouts_match_header(lib, tmp_path):
+    """ctypes mirrors of the header's structs have the sizes and field
+    offsets a C compiler gives them."""
+    import subprocess
+    from paper_2011_04130_amd import _lib as L
+    structs = {"qrng_me_opts": L.MeOpts, "qrng_me_result": L.MeResult, "qrng_block": L.Block,
+               "qrng_plan_info": L.PlanInfo, "qrng_server_cfg": L.ServerCfg,
+               "qrng_served": L.Served, "qrng_server_stats": L.ServerStats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "qrng.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in structs.items():
+        assert int(got["%s size" % cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s %s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
