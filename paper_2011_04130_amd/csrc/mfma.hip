@@ -11,7 +11,7 @@
 // output rows x 256 blocks; each wave owns 64 blocks and all 128 rows
 // (eight 32x32 accumulators).  B fragments (raw bits) are built in registers
 // from the wave's own blocks; A fragments (the Toeplitz matrix) come from an
-// LDS tile of the reversed seed window expanded to bytes, shared by the four
+// LDS copy of the reversed seed window expanded to bytes, shared by the four
 // waves.  Per 32-bit K-step a wave issues 8 MFMAs.  Fragment layout: lane l
 // holds row or column l % 32 and 16 k-values of lane group l / 32 (the same
 // k order on A and B, so the contraction over k is exact whatever the
@@ -76,18 +76,18 @@ constexpr int NTB = 4 * 32 * WNB;  // blocks per workgroup (4 waves)
 constexpr int KW = KC / 32;        // raw words per block per K-chunk
 constexpr int XROW = KW + 1;       // padded LDS row (words) of one block's chunk
 constexpr int RSPAN = MT + KC;     // bytes of one shifted copy of the seed window
-constexpr int RSTRIDE = RSPAN + 16;
+constexpr int RWORDS = RSPAN / 4 + 4;  // dwords of the window copy (+ read slack)
 constexpr int SWORDS = (RSPAN + 64) / 32 + 2;  // seed words covering the window
 
 // Workgroup tile: MT = 128 rows x NTB = 256 blocks.  Wave w owns blocks
 // 64w..64w+63 and all four 32-row tiles (8 accumulators).  A[i][k] =
 // s[n-1+i-k]: for rows i0+ri and k = k0+kk the seed index is base - u with
 // u = (MT-1) - ri + kk and base = n-1+i0-k0+MT-1, so one K-chunk needs the
-// seed bits base-u, u < MT+KC, reversed ("rs[u]").  LDS holds 16 copies
-// rs[j + c] so that every A fragment (16 consecutive u) is one aligned
-// 16-byte read.  Raw bits are staged per K-chunk with 64-byte coalesced loads.
+// seed bits base-u, u < MT+KC, reversed ("rs[u]"), one byte each in LDS.
+// An A fragment (16 consecutive u from any byte offset) is five dword reads
+// and four byte-aligns.  Raw bits are staged per K-chunk with 16-byte loads.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mfma(MfmaArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t rs[16 * RSTRIDE];
+  __shared__ uint32_t rs[RWORDS];
   __shared__ uint32_t xs[NTB * XROW];
   __shared__ uint32_t sw[SWORDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,11 +110,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int rl = lane & 31;
 
   // Global reads of one K-chunk: the seed words of its window (threads
-  // below SWORDS) and NTB*KW raw words (XPT per thread, 64-byte runs per
-  // 16 lanes).  They are issued one chunk ahead, into registers.
-  constexpr int XPT = NTB * KW / 256;
-  static_assert(NTB * KW % 256 == 0, "raw words per thread");
-  uint32_t pre_x[XPT], pre_s = 0;
+  // below SWORDS) and NTB*KW raw words, 16 bytes per load (XPT of them per
+  // thread; four lanes read one block's 64-byte run).  They are issued one
+  // chunk ahead, into registers.
+  constexpr int XPT = NTB * KW / (4 * 256);
+  static_assert(NTB * KW % (4 * 256) == 0 && KW % 4 == 0, "raw words per thread");
+  const int64_t nw32 = 2 * (((int64_t)a.n + 63) >> 6);  // readable 32-bit words of a block
+  uint4 pre_x[XPT];
+  uint32_t pre_s = 0;
   auto fetch = [&](int64_t k0) {
     const int64_t base = n - 1 + i0 - k0 + (MT - 1);
     const int64_t wlo = ((base - RSPAN - 32) >> 5);
@@ -128,15 +131,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
       const int d = tid + 256 * e;
-      const int bl = d / KW, q = d % KW;
+      const int bl = d / (KW / 4), q = 4 * (d % (KW / 4));  // words q..q+3 of the chunk
       const uint32_t b = bg + bl;
-      const int64_t kb = k0 + 32 * q;
-      uint32_t v = 0;
-      if (b < a.nblocks && kb < n) {
-        v = a.x[((uint64_t)b * a.x_zs >> 5) + (kb >> 5)];
-        if (kb + 32 > n) v &= (1u << (uint32_t)(n - kb)) - 1u;
+      const int64_t w0 = (k0 >> 5) + q;  // first word within the block
+      uint32_t v[4] = {0u, 0u, 0u, 0u};
+      if (b < a.nblocks) {
+        const uint32_t* src = a.x + ((uint64_t)b * a.x_zs >> 5) + w0;
+        if (w0 + 3 < nw32) {
+          const uint4 t = *reinterpret_cast<const uint4*>(src);
+          v[0] = t.x;
+          v[1] = t.y;
+          v[2] = t.z;
+          v[3] = t.w;
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (w0 + i < nw32) v[i] = src[i];
+        }
+        // bits at or past n read as 0
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t kb = 32 * (w0 + i);
+          if (kb >= n)
+            v[i] = 0u;
+          else if (kb + 32 > n)
+            v[i] &= (1u << (uint32_t)(n - kb)) - 1u;
+        }
       }
-      pre_x[e] = v;
+      pre_x[e] = make_uint4(v[0], v[1], v[2], v[3]);
     }
   };
   fetch(0);
@@ -147,23 +169,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
       const int d = tid + 256 * e;
-      xs[(d / KW) * XROW + d % KW] = pre_x[e];
+      uint32_t* dst = xs + (d / (KW / 4)) * XROW + 4 * (d % (KW / 4));
+      dst[0] = pre_x[e].x;
+      dst[1] = pre_x[e].y;
+      dst[2] = pre_x[e].z;
+      dst[3] = pre_x[e].w;
     }
     if (k0 + KC < n) fetch(k0 + KC);
     __syncthreads();
-    // copy c, dword j: bytes rs[4j+c .. 4j+c+3] = seed bits base-(4j+c) down to base-(4j+c)-3
-    for (int d = tid; d < 16 * (RSTRIDE / 4); d += 256) {
-      const int c = d / (RSTRIDE / 4), j = d % (RSTRIDE / 4);
-      const int64_t p = base - (4 * j + c) - 3 - 32 * wlo;  // bit offset in sw
+    // dword j: bytes 4j .. 4j+3 = seed bits base-4j down to base-4j-3
+    for (int j = tid; j < RWORDS; j += 256) {
+      const int64_t p = base - 4 * j - 3 - 32 * wlo;  // bit offset in sw
       const int pw = (int)(p >> 5), ps = (int)(p & 31);
       uint32_t w4 = sw[pw] >> ps;
       if (ps > 28) w4 |= sw[pw + 1] << (32 - ps);
       const uint32_t rev = (__builtin_bitreverse32(w4 & 15u) >> 28) & 15u;
-      *reinterpret_cast<uint32_t*>(rs + c * RSTRIDE + 4 * j) = expand4(rev);
+      rs[j] = expand4(rev);
     }
     __syncthreads();
+    // A fragment of row tile t at K-step ks: rows ri = 32t + rl, k offset
+    // kk = 32 ks + kg, u0 = MT-1 - ri + kk.  The matrix is Toeplitz, so
+    // (t, ks) and (t+1, ks+1) have the same u0: after the first K-step of a
+    // chunk only tile 0's fragment is new, the others move down one tile.
+    auto a_frag = [&](int t, int ks) {
+      const int u0 = (MT - 1) - (32 * t + rl) + 32 * ks + kg;
+      const int w = u0 >> 2;
+      const uint32_t sh = (uint32_t)(u0 & 3);
+      const uint32_t d0 = rs[w], d1 = rs[w + 1], d2 = rs[w + 2], d3 = rs[w + 3], d4 = rs[w + 4];
+      v4i f;
+      f.x = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
+      f.y = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
+      f.z = (int)__builtin_amdgcn_alignbyte(d3, d2, sh);
+      f.w = (int)__builtin_amdgcn_alignbyte(d4, d3, sh);
+      return f;
+    };
+    v4i af[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) af[t] = a_frag(t, 0);
 #pragma unroll
     for (int ks = 0; ks < KW; ++ks) {
+      if (ks > 0) {
+        af[3] = af[2];
+        af[2] = af[1];
+        af[1] = af[0];
+        af[0] = a_frag(0, ks);
+      }
       v4i bf[WNB];
 #pragma unroll
       for (int u = 0; u < WNB; ++u) {
@@ -171,14 +221,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         bf[u] = expand16((xs[bl * XROW + ks] >> kg) & 0xFFFFu);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        // rows ri = 32t + rl, k offset kk = 32 ks + kg: u0 = MT-1 - ri + kk
-        const int u0 = (MT - 1) - (32 * t + rl) + 32 * ks + kg;
-        const v4i af = *reinterpret_cast<const v4i*>(rs + (u0 & 15) * RSTRIDE + (u0 & ~15));
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int u = 0; u < WNB; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af, bf[u], acc[t][u], 0, 0, 0);
-      }
+          acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[t], bf[u], acc[t][u], 0, 0, 0);
     }
     __syncthreads();
   }
