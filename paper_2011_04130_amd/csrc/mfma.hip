@@ -77,7 +77,6 @@ constexpr int KW = KC / 32;        // raw words per block per K-chunk
 constexpr int XROW = KW + 1;       // padded LDS row (words) of one block's chunk
 constexpr int RSPAN = MT + KC;     // bytes of one shifted copy of the seed window
 constexpr int RWORDS = RSPAN / 4 + 4;  // dwords of the window copy (+ read slack)
-constexpr int SWORDS = (RSPAN + 64) / 32 + 2;  // seed words covering the window
 
 // Workgroup tile: MT = 128 rows x NTB = 256 blocks.  Wave w owns blocks
 // 64w..64w+63 and all four 32-row tiles (8 accumulators).  A[i][k] =
@@ -87,9 +86,10 @@ constexpr int SWORDS = (RSPAN + 64) / 32 + 2;  // seed words covering the window
 // An A fragment (16 consecutive u from any byte offset) is five dword reads
 // and four byte-aligns.  Raw bits are staged per K-chunk with 16-byte loads.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mfma(MfmaArgs a) {
-  __shared__ uint32_t rs[RWORDS];
-  __shared__ uint32_t xs[NTB * XROW];
-  __shared__ uint32_t sw[SWORDS];
+  // two buffers: chunk k is multiplied from one while chunk k+1 is staged
+  // into the other, so each chunk needs one barrier
+  __shared__ uint32_t rs[2][RWORDS];
+  __shared__ uint32_t xs[2][NTB * XROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * MT;
   const int64_t n = (int64_t)a.n, L = (int64_t)a.L;
@@ -109,34 +109,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int kg = 16 * (lane >> 5);  // lane group's k offset within a K-step
   const int rl = lane & 31;
 
-  // Global reads of one K-chunk: the seed words of its window (threads
-  // below SWORDS) and NTB*KW raw words, 16 bytes per load (XPT of them per
-  // thread; four lanes read one block's 64-byte run).  They are issued one
-  // chunk ahead, into registers.
+  // Global reads of one K-chunk, issued one chunk ahead into registers:
+  // NTB*KW raw words, 16 bytes per load (XPT per thread; four lanes read
+  // one block's 64-byte run), and for threads j < RWORDS the two seed words
+  // that hold window dword j's four bits.
   constexpr int XPT = NTB * KW / (4 * 256);
   static_assert(NTB * KW % (4 * 256) == 0 && KW % 4 == 0, "raw words per thread");
+  static_assert(RWORDS <= 256, "one window dword per thread");
   const int64_t nw32 = 2 * (((int64_t)a.n + 63) >> 6);  // readable 32-bit words of a block
+  // thread's raw rows: block bg + tid/4 + 64 e, words 4 (tid % 4) .. + 3
+  const uint32_t b0 = bg + (uint32_t)(tid >> 2);
+  const int q0 = 4 * (tid & 3);
+  const uint64_t bstride = (uint64_t)64 * a.x_zs >> 5;  // words between e and e+1
+  const uint32_t* xrow = a.x + ((uint64_t)b0 * a.x_zs >> 5) + q0;
+  const bool full_group = bg + NTB <= a.nblocks;
   uint4 pre_x[XPT];
-  uint32_t pre_s = 0;
+  uint32_t pre_s0 = 0, pre_s1 = 0;
+  auto seed_word = [&](int64_t w) -> uint32_t {
+    uint32_t v = (w >= 0 && w < nsw) ? a.seed[w] : 0u;
+    const int64_t top = L - 32 * w;  // bits of word w below L
+    if (top < 32) v &= top <= 0 ? 0u : ((1u << (uint32_t)top) - 1u);
+    return v;
+  };
   auto fetch = [&](int64_t k0) {
     const int64_t base = n - 1 + i0 - k0 + (MT - 1);
-    const int64_t wlo = ((base - RSPAN - 32) >> 5);
-    if (tid < SWORDS) {
-      const int64_t w = wlo + tid;
-      uint32_t v = (w >= 0 && w < nsw) ? a.seed[w] : 0u;
-      const int64_t top = L - 32 * w;  // bits of word w below L
-      if (top < 32) v &= top <= 0 ? 0u : ((1u << (uint32_t)top) - 1u);
-      pre_s = v;
+    if (tid < RWORDS) {
+      // window dword tid: seed bits base-4 tid-3 .. base-4 tid
+      const int64_t p = base - 4 * tid - 3;
+      const int64_t w = p >> 5;  // floor
+      pre_s0 = seed_word(w);
+      pre_s1 = ((p & 31) > 28) ? seed_word(w + 1) : 0u;
+    }
+    const int64_t kw = k0 >> 5;
+    if (full_group && k0 + KC <= n) {
+      // whole chunk inside every block: plain 16-byte loads
+#pragma unroll
+      for (int e = 0; e < XPT; ++e)
+        pre_x[e] = *reinterpret_cast<const uint4*>(xrow + e * bstride + kw);
+      return;
     }
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
-      const int d = tid + 256 * e;
-      const int bl = d / (KW / 4), q = 4 * (d % (KW / 4));  // words q..q+3 of the chunk
-      const uint32_t b = bg + bl;
-      const int64_t w0 = (k0 >> 5) + q;  // first word within the block
+      const uint32_t b = b0 + 64 * e;
+      const int64_t w0 = kw + q0;  // first word within the block
       uint32_t v[4] = {0u, 0u, 0u, 0u};
       if (b < a.nblocks) {
-        const uint32_t* src = a.x + ((uint64_t)b * a.x_zs >> 5) + w0;
+        const uint32_t* src = xrow + e * bstride + kw;
         if (w0 + 3 < nw32) {
           const uint4 t = *reinterpret_cast<const uint4*>(src);
           v[0] = t.x;
@@ -161,32 +179,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       pre_x[e] = make_uint4(v[0], v[1], v[2], v[3]);
     }
   };
-  fetch(0);
-  for (int64_t k0 = 0; k0 < n; k0 += KC) {
-    const int64_t base = n - 1 + i0 - k0 + (MT - 1);
-    const int64_t wlo = ((base - RSPAN - 32) >> 5);
-    if (tid < SWORDS) sw[tid] = pre_s;
+  // write the prefetched chunk (window start base) into buffer c
+  auto stage = [&](int c, int64_t k0) {
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
-      const int d = tid + 256 * e;
-      uint32_t* dst = xs + (d / (KW / 4)) * XROW + 4 * (d % (KW / 4));
+      uint32_t* dst = xs[c] + ((tid >> 2) + 64 * e) * XROW + q0;
       dst[0] = pre_x[e].x;
       dst[1] = pre_x[e].y;
       dst[2] = pre_x[e].z;
       dst[3] = pre_x[e].w;
     }
-    if (k0 + KC < n) fetch(k0 + KC);
-    __syncthreads();
-    // dword j: bytes 4j .. 4j+3 = seed bits base-4j down to base-4j-3
-    for (int j = tid; j < RWORDS; j += 256) {
-      const int64_t p = base - 4 * j - 3 - 32 * wlo;  // bit offset in sw
-      const int pw = (int)(p >> 5), ps = (int)(p & 31);
-      uint32_t w4 = sw[pw] >> ps;
-      if (ps > 28) w4 |= sw[pw + 1] << (32 - ps);
+    if (tid < RWORDS) {
+      // bytes 4j .. 4j+3 = seed bits base-4j down to base-4j-3 (j = tid)
+      const int64_t base = n - 1 + i0 - k0 + (MT - 1);
+      const uint32_t ps = (uint32_t)((base - 4 * tid - 3) & 31);
+      uint32_t w4 = pre_s0 >> ps;
+      if (ps > 28) w4 |= pre_s1 << (32 - ps);
       const uint32_t rev = (__builtin_bitreverse32(w4 & 15u) >> 28) & 15u;
-      rs[j] = expand4(rev);
+      rs[c][tid] = expand4(rev);
     }
-    __syncthreads();
+  };
+  fetch(0);
+  stage(0, 0);
+  __syncthreads();
+  int c = 0;
+  for (int64_t k0 = 0; k0 < n; k0 += KC, c ^= 1) {
+    const bool more = k0 + KC < n;
+    if (more) fetch(k0 + KC);
+    const uint32_t* rsc = rs[c];
+    const uint32_t* xsc = xs[c];
     // A fragment of row tile t at K-step ks: rows ri = 32t + rl, k offset
     // kk = 32 ks + kg, u0 = MT-1 - ri + kk.  The matrix is Toeplitz, so
     // (t, ks) and (t+1, ks+1) have the same u0: after the first K-step of a
@@ -195,7 +216,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int u0 = (MT - 1) - (32 * t + rl) + 32 * ks + kg;
       const int w = u0 >> 2;
       const uint32_t sh = (uint32_t)(u0 & 3);
-      const uint32_t d0 = rs[w], d1 = rs[w + 1], d2 = rs[w + 2], d3 = rs[w + 3], d4 = rs[w + 4];
+      const uint32_t d0 = rsc[w], d1 = rsc[w + 1], d2 = rsc[w + 2], d3 = rsc[w + 3],
+                     d4 = rsc[w + 4];
       v4i f;
       f.x = (int)__builtin_amdgcn_alignbyte(d1, d0, sh);
       f.y = (int)__builtin_amdgcn_alignbyte(d2, d1, sh);
@@ -218,7 +240,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int u = 0; u < WNB; ++u) {
         const int bl = wave * 32 * WNB + 32 * u + rl;
-        bf[u] = expand16((xs[bl * XROW + ks] >> kg) & 0xFFFFu);
+        bf[u] = expand16((xsc[bl * XROW + ks] >> kg) & 0xFFFFu);
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t)
@@ -226,6 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int u = 0; u < WNB; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[t], bf[u], acc[t][u], 0, 0, 0);
     }
+    if (more) stage(c ^ 1, k0 + KC);
     __syncthreads();
   }
 
