@@ -81,7 +81,10 @@ def algorithmic_work(kernel, n, m, batch=1):
         Nc, N1, N2 = 1 << p["log_nc"], 1 << p["log1"], 1 << p["log2"]
         twid = Nc - N1 - N2 + 1
         if kernel == "ntt_rows_hash":
-            mm = (p["nx"] + p["ny"]) * N1 * radix2_modmuls(N2) + p["nx"] * p["ny"] * Nc
+            # pointwise products: one per (raw, output) chunk pair, except
+            # that a 2 x 2 block Toeplitz product needs three
+            prods = 3 if (p["nx"], p["ny"]) == (2, 2) else p["nx"] * p["ny"]
+            mm = (p["nx"] + p["ny"]) * N1 * radix2_modmuls(N2) + prods * Nc
             return 3 * mm * batch, "int32 mul"
         if kernel == "ntt_cols_fwd":
             return 3 * p["nx"] * batch * (N2 * radix2_modmuls(N1) + twid), "int32 mul"

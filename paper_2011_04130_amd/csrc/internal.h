@@ -75,7 +75,8 @@ uint64_t ntt_work_elems(const NttPlan& p, int batch);
 // Transform-domain seed: nwin arrays of Nc words (Montgomery form, 1/Nc folded).
 // With one transform (nx = ny = 1) the spectrum is that of the seed's first
 // Nc bits (seed_avail bits exist; the rest read as 0) and depends on the seed
-// and Nc only; above 2^23 it depends on (n, m).
+// and Nc only; above 2^23 it depends on (n, m).  With two raw and two output
+// chunks the three windows are stored as (W1, W0 - W1, W2 - W1).
 hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_t n,
                             uint64_t m, uint64_t seed_avail, uint32_t* W, uint32_t* work,
                             const TwTables& tw, hipStream_t s);

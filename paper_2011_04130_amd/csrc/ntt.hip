@@ -552,13 +552,60 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
     }
     return;
   } else {
+    // Two raw and two output chunks: the 2x2 block matrix is [[A, B], [C, A]]
+    // (the diagonal blocks share a window), so with spectra stored as
+    // (A, B-A, C-A) three products do: m1 = A (x0+x1), y0 = m1 + (B-A) x1,
+    // y1 = m1 + (C-A) x0.  m1 takes x1's registers (x1 is not needed after
+    // y0's products).
+    const bool three = NX == 2 && a.ny == 2;
     for (int o = 0; o < a.ny; ++o) {
       uint32_t acc[GPT][16];
 #pragma unroll
       for (int u = 0; u < GPT; ++u)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[u][e] = 0;
-      static_for<0, NX>([&](auto cc) {
+      if constexpr (NX == 2) {
+        if (three) {
+          const uint32_t* wrow = a.W + (uint64_t)row * N2;
+          if (o == 0) {
+            // m1 = A (x0 + x1); acc = m1 + (B - A) x1
+#pragma unroll
+            for (int u = 0; u < GPT; ++u) {
+              const uint32_t* wa = wrow + (tid + u * T) * 4;
+              const uint32_t* wb = wa + (uint32_t)Nc;
+#pragma unroll
+              for (int e = 0; e < 16; e += 4) {
+                const uint4 va = *reinterpret_cast<const uint4*>(wa + (e / 4) * (N2 / 4));
+                const uint4 vb = *reinterpret_cast<const uint4*>(wb + (e / 4) * (N2 / 4));
+                const uint32_t A4[4] = {va.x, va.y, va.z, va.w};
+                const uint32_t B4[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  const uint32_t x1 = xs[NX - 1][u][e + i];
+                  const uint32_t mm = mul_mont(red2(xs[0][u][e + i] + x1), A4[i]);
+                  acc[u][e + i] = red2(mm + mul_mont(x1, B4[i]));
+                  xs[NX - 1][u][e + i] = mm;
+                }
+              }
+            }
+          } else {
+            // acc = m1 + (C - A) x0
+#pragma unroll
+            for (int u = 0; u < GPT; ++u) {
+              const uint32_t* wc = wrow + 2 * (uint64_t)(uint32_t)Nc + (tid + u * T) * 4;
+#pragma unroll
+              for (int e = 0; e < 16; e += 4) {
+                const uint4 vc = *reinterpret_cast<const uint4*>(wc + (e / 4) * (N2 / 4));
+                const uint32_t C4[4] = {vc.x, vc.y, vc.z, vc.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  acc[u][e + i] = red2(xs[NX - 1][u][e + i] + mul_mont(xs[0][u][e + i], C4[i]));
+              }
+            }
+          }
+        }
+      }
+      if (!three) static_for<0, NX>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         const uint32_t* wr = (desc ? desc->W : a.W + (uint64_t)(o - c + NX - 1) * (uint32_t)Nc) +
                              (uint64_t)row * N2;
@@ -612,6 +659,17 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
       __syncthreads();
     }
   }
+}
+
+// Two raw and two output chunks: windows (W0, W1, W2) -> (W1, W0 - W1,
+// W2 - W1), the order the three-product row pass reads (values in [0, p)).
+__global__ __launch_bounds__(256) void k_combine3(uint32_t* __restrict__ W, uint32_t Nc) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= Nc) return;
+  const uint32_t a = W[i], b = W[Nc + i], c = W[2 * (uint64_t)Nc + i];
+  W[i] = b;
+  W[Nc + i] = a >= b ? a - b : a + P - b;
+  W[2 * (uint64_t)Nc + i] = c >= b ? c - b : c + P - b;
 }
 
 // ------------------------------------------------------------ dispatch
@@ -833,7 +891,11 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
   hipError_t e = cols_fwd(p.log1, c, dim3((1u << p.log2) / COLS, p.nwin), tw, s);
   if (e != hipSuccess) return e;
   r.in = work;
-  return rows_l<1, false, true, false>(p.log2, r, dim3(1u << p.log1, p.nwin), tw, s);
+  e = rows_l<1, false, true, false>(p.log2, r, dim3(1u << p.log1, p.nwin), tw, s);
+  if (e != hipSuccess || !(p.nx == 2 && p.ny == 2)) return e;
+  hipLaunchKernelGGL(k_combine3, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, s, W,
+                     (uint32_t)Nc);
+  return hipGetLastError();
 }
 
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
