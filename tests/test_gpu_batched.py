@@ -90,3 +90,49 @@ def test_mfma_single_block_and_sweep_slice(torch, ctx):
         assert np.array_equal(y1, outs[1][40:80])
     finally:
         ctx.unregister_seed(sid)
+
+
+@pytest.fixture(scope="module")
+def sweep_stream(torch):
+    """The block-length sweep's 2^30-bit raw sequence (2^27 Gaussian samples)."""
+    c = qi.config(2)
+    s = qi.gen_adc(c["S"], c["sigma"], seed=c["adc_seed"])
+    return c, qi.samples_as_words(s), dev(torch, qi.samples_as_words(s))
+
+
+@pytest.mark.parametrize("lg", [12, 14, 16, 18, 20, 22, 24])
+def test_sweep_full_size_sampled_blocks(torch, ctx, sweep_stream, lg):
+    """The sweep at its full size, in the launch the bench times (one strided
+    call over all 2^30/n blocks): up to 2^14 every path's whole output agrees
+    with the others; the first, last and two random blocks agree with the
+    oracle (whole blocks up to 2^16 bits, sampled rows above)."""
+    c, xw, xt = sweep_stream
+    n = 1 << lg
+    m = n * c["gamma_num"] // c["gamma_den"]
+    B = c["total_bits"] // n
+    log("sweep n=2^%d blocks=%d" % (lg, B))
+    sw = qi.gen_seed_words(n + m - 1, c["seed_seed"])
+    sid = ctx.register_seed(dev(torch, sw), n + m - 1)
+    yw = (m + 63) // 64
+    try:
+        paths = (0, 2, 3, 1) if lg <= 14 else (0,)
+        outs = {}
+        for path in paths:
+            yt = torch.empty(B * yw, dtype=torch.int64, device="cuda:0")
+            ctx.hash_strided(xt, n, n // 64, sid, m, yt, yw, B, path=path)
+            outs[path] = host(yt)
+        for path in paths[1:]:
+            assert np.array_equal(outs[0], outs[path]), "path %d differs from auto" % path
+        got = outs[0]
+        rng = np.random.default_rng(lg)
+        for b in sorted({0, B - 1, *rng.integers(0, B, 2).tolist()}):
+            xb = xw[b * (n // 64):(b + 1) * (n // 64)]
+            yb = got[b * yw:(b + 1) * yw]
+            if n <= (1 << 16):
+                assert np.array_equal(yb, oracle.toeplitz_packed(xb, n, sw, m)), "block %d" % b
+            else:
+                rows = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, 24)]))
+                want = oracle.toeplitz_rows(xb, n, sw, n + m - 1, rows)
+                assert np.array_equal(oracle.unpack_bits(yb, m)[rows], want), "block %d" % b
+    finally:
+        ctx.unregister_seed(sid)

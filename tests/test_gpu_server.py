@@ -258,3 +258,42 @@ def test_server_vector_calls(torch, ctx, windows, seed):
     for rid in ids:
         s, w = done[int(rid)]
         assert np.array_equal(w, want_bits(windows, sw, s, NS))
+
+
+def test_server_full_size_windows(torch, ctx):
+    """Windows of 2^24 samples (the serving workload's size) with the block
+    length chosen by timing: requests of log-uniform size served in a mix,
+    each checked against the oracle (whole requests up to 2^18 bits, the
+    first and last block of larger ones)."""
+    cfg = qi.config(4)
+    Wf = cfg["window_samples"]
+    wins = [qi.gen_adc(Wf, cfg["sigma"], seed=cfg["adc_seed"] + k) for k in range(2)]
+    L = 1 << 19
+    sw = qi.gen_seed_words(L, cfg["seed_seed"])
+    sid = ctx.register_seed(torch.from_numpy(sw.view(np.int64).copy()).to("cuda:0"), L)
+    try:
+        with ctx.server(sid, Wf, block_bits=0, ring_bits=1 << 30, window_slots=2) as srv:
+            n = srv.stats()["block_bits"]
+            log("full-size serving, n_s=%d" % n)
+            sizes = qi.request_sizes(60, cfg["r_log2_min"], cfg["r_log2_max"], cfg["arrival_seed"])
+            ids, out = serve_all(torch, srv, wins, sizes)
+        rng = np.random.default_rng(1)
+        for rid in rng.choice(ids, 12, replace=False):
+            s, w = out[rid]
+            assert s["status"] == 0
+            assert s["m_block"] == m_block(wins[s["window"]], n)
+            if s["bits"] <= (1 << 18):
+                assert np.array_equal(w, want_bits(wins, sw, s, n)), "request %d" % rid
+            else:
+                x = qi.samples_as_words(wins[s["window"]])
+                mb = s["m_block"]
+                bits = oracle.unpack_bits(w, s["bits"])
+                for j in (0, s["blocks"] - 1):
+                    b = s["first_block"] + j
+                    yb = oracle.toeplitz_packed(x[b * n // 64:(b + 1) * n // 64], n, sw, mb)
+                    want = oracle.unpack_bits(yb, mb)
+                    lo = j * mb
+                    hi = min(lo + mb, s["bits"])
+                    assert np.array_equal(bits[lo:hi], want[:hi - lo]), "request %d" % rid
+    finally:
+        ctx.unregister_seed(sid)
