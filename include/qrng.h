@@ -50,7 +50,7 @@ typedef enum {
 /* Which extraction kernel to run.  All paths return identical bits. */
 typedef enum {
   QRNG_PATH_AUTO = 0,   /* library picks (autotuned plan table if loaded) */
-  QRNG_PATH_DIRECT = 1, /* bit-packed AND/parity mat-vec, O(mn) */
+  QRNG_PATH_DIRECT = 1, /* bit-packed AND/parity mat-vec, O(mn); n+m-1 < 2^34 */
   QRNG_PATH_NTT = 2,    /* exact convolution mod 998244353, O(L log L) */
   QRNG_PATH_MFMA = 3    /* int8 matrix-core product, shared-seed batches */
 } qrng_path;

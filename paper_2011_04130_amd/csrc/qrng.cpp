@@ -209,6 +209,9 @@ int choose_path(uint64_t n, uint64_t m, uint64_t batch = 1) {
 qrng_status run_direct(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                        uint64_t m, uint64_t* y, hipStream_t s, int batch, uint64_t xs,
                        uint64_t ys, const uint64_t* m_dev) {
+  // the seed is read through a buffer resource with 32-bit byte offsets
+  if (n + m - 1 >= (1ull << 34))
+    return fail(QRNG_EINVAL, "direct path: n + m - 1 must be below 2^34");
   qrng_status st = ensure_work(ctx, direct_work_words(n, batch));
   if (st) return st;
   HIP_TRY(direct_hash(reinterpret_cast<const uint32_t*>(x), n,
