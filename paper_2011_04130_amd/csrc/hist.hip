@@ -22,6 +22,7 @@ namespace qrng {
 namespace {
 
 constexpr int HB = 257;  // 256 values + out-of-range
+constexpr int PS = 260;  // row stride of the partial counts (16-byte rows)
 
 // ------------------------------------------------------- wave reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -208,7 +209,7 @@ struct HistArgs {
   const uint8_t* s;
   uint64_t S;
   int N;
-  uint32_t* part;               // G x HB partial counts (fully overwritten)
+  uint32_t* part;               // G rows of PS words: HB partial counts, zero pad
   uint32_t G;                   // workgroups of the counting launch
   unsigned long long* counts;   // nullable: the 2^N + 1 summed counts
   bool finish;                  // run the estimate (MeDevArgs below)
@@ -264,8 +265,8 @@ __global__ __launch_bounds__(256) void k_hist_part(HistArgs a) {
     }
   }
   __syncthreads();
-  uint32_t* mine = a.part + (uint64_t)blockIdx.x * HB;
-  for (int b = tid; b < HB; b += 256) mine[b] = merged(h, b);
+  uint32_t* mine = a.part + (uint64_t)blockIdx.x * PS;
+  for (int b = tid; b < PS; b += 256) mine[b] = b < HB ? merged(h, b) : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_hist_finish(HistArgs a) {
@@ -273,23 +274,53 @@ __global__ __launch_bounds__(256) void k_hist_finish(HistArgs a) {
   const int tid = threadIdx.x;
   const uint32_t lim = 1u << a.N;
   const uint64_t G = a.G;
-  // thread b adds bin b over the G partials (written by other dies: each
-  // load misses the local L2, so 16 are kept in flight); thread 0 also adds
-  // the out-of-range bin
-  auto column = [&](const uint32_t* p) {
-    uint64_t t = 0, g = 0;
-    for (; g + 16 <= G; g += 16) {
-      uint32_t x[16];
+  // The G partial rows were written by other dies, so every load misses the
+  // local L2 and costs a full round trip: thread (q, c) adds bins 4c..4c+3
+  // over quarter q of the rows with 16-byte loads, 16 in flight (one round
+  // trip for the usual G <= 64); threads 0..63 add the out-of-range bin over
+  // rows g = tid mod 64.  Thread b then owns bin b.
+  __shared__ unsigned long long qs[4][256];
+  __shared__ unsigned long long oobs[64];
+  {
+    const int c = tid & 63, q = tid >> 6;
+    const uint64_t g0 = q * G / 4, g1 = (q + 1) * G / 4;
+    const uint4* __restrict__ p4 = reinterpret_cast<const uint4*>(a.part) + c;
+    unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    uint64_t g = g0;
+    for (; g + 16 <= g1; g += 16) {
+      uint4 x[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = p[(g + k) * HB];
+      for (int k = 0; k < 16; ++k) x[k] = p4[(g + k) * (PS / 4)];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) t += x[k];
+      for (int k = 0; k < 16; ++k) {
+        s0 += x[k].x;
+        s1 += x[k].y;
+        s2 += x[k].z;
+        s3 += x[k].w;
+      }
     }
-    for (; g < G; ++g) t += p[g * HB];
-    return t;
-  };
-  const uint64_t t = column(a.part + tid);
-  const uint64_t o = tid == 0 ? column(a.part + 256) : 0;
+    for (; g < g1; ++g) {
+      const uint4 x = p4[g * (PS / 4)];
+      s0 += x.x;
+      s1 += x.y;
+      s2 += x.z;
+      s3 += x.w;
+    }
+    qs[q][4 * c] = s0;
+    qs[q][4 * c + 1] = s1;
+    qs[q][4 * c + 2] = s2;
+    qs[q][4 * c + 3] = s3;
+    if (tid < 64) {
+      unsigned long long o = 0;
+      for (uint64_t r = tid; r < G; r += 64) o += a.part[r * PS + 256];
+      oobs[tid] = o;
+    }
+  }
+  __syncthreads();
+  const uint64_t t = qs[0][tid] + qs[1][tid] + qs[2][tid] + qs[3][tid];
+  uint64_t o = 0;
+  if (tid == 0)
+    for (int r = 0; r < 64; ++r) o += oobs[r];
   if (a.counts) {
     if (tid < (int)lim) a.counts[tid] = t;
     if (tid == 0) a.counts[lim] = o;
@@ -347,7 +378,7 @@ unsigned hist_groups(uint64_t S) {
 
 }  // namespace
 
-uint64_t hist_scratch_words() { return (uint64_t)HIST_MAX_GROUPS * HB; }
+uint64_t hist_scratch_words() { return (uint64_t)HIST_MAX_GROUPS * PS; }
 
 hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
                          unsigned long long* counts_out, const MeDevArgs* finish,
