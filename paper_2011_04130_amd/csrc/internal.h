@@ -28,6 +28,20 @@ const char* kernel_name(int kid);
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
 
+// Min-entropy finish on the device: model, H_min, d_U, Delta H_m, H_modify
+// from the counts, and m = n H/N - 2 log2(1/eps) (whole bits per sample,
+// clamped to [0, m_cap]).  `out` is a qrng_me_result (nullable), m_out a
+// uint64 (nullable).
+struct MeDevArgs {
+  int N, model, u_mode;
+  double mu, sigma;
+  uint64_t n;
+  double log2_inv_eps;
+  uint64_t m_cap;
+  void* out;
+  uint64_t* m_out;
+};
+
 // ---------------------------------------------------------------- NTT path
 // Per-sub-length twiddle tables (w, floor(w 2^32/p)) and the two-level
 // Montgomery table of the 2^23-rd root used by the four-step twiddles.
@@ -90,10 +104,24 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
 hipError_t ntt_hash_items(const NttPlan& p, const uint32_t* x_pool, const NttItem* items,
                           int count, uint32_t* y_pool, const uint64_t* m_arr, uint32_t* work,
                           const TwTables& tw, hipStream_t s);
+// The min-entropy estimate of one block's 8-bit samples run inside the
+// hash's first transform pass (extra workgroups; the estimate's m_out is the
+// hash's m_dev).  scratch: hist_scratch_words() words, zero on first use and
+// left zero by every call.
+struct EstJob {
+  const uint8_t* samples;
+  uint64_t S;
+  uint32_t* scratch;
+  MeDevArgs me;
+};
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
                     uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
-                    hipStream_t s, const uint64_t* m_dev = nullptr);
+                    hipStream_t s, const uint64_t* m_dev = nullptr,
+                    const EstJob* est = nullptr);
+// whether ntt_hash with this plan takes an EstJob (one block, split transform
+// with columns of at least 2^7)
+bool ntt_fuses_estimate(const NttPlan& p);
 
 // ------------------------------------------------------------- direct path
 // `batch` blocks sharing one seed: block z reads x_bits + z*x_stride_bits and
@@ -112,23 +140,10 @@ hipError_t mfma_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bi
                      uint64_t y_stride_bits, hipStream_t s, const uint64_t* m_dev = nullptr);
 
 // ------------------------------------------------------- histogram, estimate
-// Min-entropy finish on the device: model, H_min, d_U, Delta H_m, H_modify
-// from the counts, and m = n H/N - 2 log2(1/eps) (whole bits per sample,
-// clamped to [0, m_cap]).  `out` is a qrng_me_result (nullable), m_out a
-// uint64 (nullable).
-struct MeDevArgs {
-  int N, model, u_mode;
-  double mu, sigma;
-  uint64_t n;
-  double log2_inv_eps;
-  uint64_t m_cap;
-  void* out;
-  uint64_t* m_out;
-};
-
 constexpr int HIST_MAX_GROUPS = 256;
-// uint32 words of the scratch (partial histograms) one hist_estimate call
-// uses; calls that share it must be ordered on one stream.
+// uint32 words of the scratch (partial histograms and a ticket) one
+// hist_estimate call or fused estimate uses; calls that share it must be
+// ordered on one stream.
 uint64_t hist_scratch_words();
 // Two launches: histogram of S samples of N bits (N <= 8); counts_out
 // (nullable, device) receives the 2^N counts and then the number of samples

@@ -35,6 +35,7 @@
 #include <utility>
 
 #include "common.h"
+#include "hist_dev.h"
 #include "internal.h"
 
 namespace qrng {
@@ -253,19 +254,42 @@ struct ColFwdArgs {
   int log2, log_nc;
   uint32_t* out;  // item y = blockIdx.y at out + y * Nc
   const NttItem* items;  // non-null: item y is the raw block items[y] (nmap = 1)
+  // hg > 0: workgroups x < hg of item 0 count samples for the min-entropy
+  // estimate instead (those of other items exit), the last of them runs it
+  uint32_t hg;
+  uint32_t* ticket;
+  hd::HistArgs est;
 };
 
 constexpr int COLS = 32;    // columns per workgroup (128-byte rows)
 constexpr int CSLOTS = 16;  // 512 threads = 32 columns x 16 slots
 constexpr int CGMAX = 2;    // groups in flight per thread
 
+// sub-histogram copies of an estimate workgroup in the column LDS
+template <int LOG1>
+constexpr int est_copies() {
+  return LOG1 >= 9 ? 32 : (LOG1 == 8 ? 16 : 8);
+}
+
 template <int LOG1>
 __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTables tw) {
-  __shared__ uint32_t lds[(1 << LOG1) * COLS];
+  __shared__ __align__(16) uint32_t lds[(1 << LOG1) * COLS];
   __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
+  if (blockIdx.x < a.hg) {
+    if constexpr (LOG1 >= 7) {
+      static_assert(est_copies<LOG1>() * hd::HB <= (1 << LOG1) * COLS &&
+                        sizeof(hd::FinishLds) <= sizeof(lds),
+                    "estimate workgroup fits the column LDS");
+      if (blockIdx.y == 0)
+        hd::estimate_workgroup<COLS * CSLOTS, est_copies<LOG1>()>(a.est, blockIdx.x, a.ticket,
+                                                                  lds);
+    }
+    return;
+  }
+  const int bx = blockIdx.x - a.hg;  // column block
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int32_t Nc = 1 << a.log_nc;
-  const int j2 = blockIdx.x * COLS + c;
+  const int j2 = bx * COLS + c;
   const uint32_t* __restrict__ bits;
   BitMap mp;
   if (a.items) {
@@ -281,7 +305,7 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
   const int l2 = a.log2;
 
   for (int j1 = threadIdx.x; j1 < (1 << LOG1); j1 += COLS * CSLOTS)
-    wbits[j1] = stage_word(bits, mp, (j1 << l2) + (int)blockIdx.x * COLS, Nc);
+    wbits[j1] = stage_word(bits, mp, (j1 << l2) + bx * COLS, Nc);
   __syncthreads();
   auto ld_bits = [&](int g, int e) -> uint32_t {
     const int j1 = Geo<LOG1, 0>::pos0(g) + e * Geo<LOG1, 0>::s;
@@ -901,8 +925,9 @@ hipError_t ntt_seed_spectra(const NttPlan& p, const uint32_t* seed_bits, uint64_
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
                     uint64_t x_stride_bits, uint64_t y_stride_bits, const TwTables& tw,
-                    hipStream_t s, const uint64_t* m_dev) {
+                    hipStream_t s, const uint64_t* m_dev, const EstJob* est) {
   const int64_t Nc = (int64_t)1 << p.log_nc;
+  if (est && (batch != 1 || !ntt_fuses_estimate(p))) return hipErrorInvalidValue;
   RowArgs r{};
   r.W = W;
   r.nx = p.nx;
@@ -933,7 +958,19 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   c.log2 = p.log2;
   c.log_nc = p.log_nc;
   c.out = X;
-  hipError_t e = cols_fwd(p.log1, c, dim3((1u << p.log2) / COLS, batch * p.nx), tw, s);
+  if (est) {
+    c.est.s = est->samples;
+    c.est.S = est->S;
+    c.est.N = 8;
+    c.est.part = est->scratch;
+    c.est.G = hd::hist_groups(est->S);
+    c.est.counts = nullptr;
+    c.est.finish = true;
+    c.est.me = est->me;
+    c.hg = c.est.G;
+    c.ticket = est->scratch + hd::TICKET_WORD;
+  }
+  hipError_t e = cols_fwd(p.log1, c, dim3((1u << p.log2) / COLS + c.hg, batch * p.nx), tw, s);
   if (e != hipSuccess) return e;
   r.in = X;
   r.out = Z;
@@ -958,6 +995,8 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   ci.m_dev = m_dev;
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, batch * p.ny), tw, s);
 }
+
+bool ntt_fuses_estimate(const NttPlan& p) { return p.log1 >= 7; }
 
 bool ntt_plan_for_length(int log_nc, NttPlan* p) {
   if (log_nc < 10 || log_nc > LOG_MAX) return false;

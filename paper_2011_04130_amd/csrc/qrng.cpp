@@ -223,7 +223,8 @@ qrng_status run_direct(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint6
 // NTT hash; W == nullptr computes the seed windows into the workspace first.
 qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                     const uint32_t* W, uint64_t m, uint64_t* y, hipStream_t s, int batch,
-                    uint64_t xs, uint64_t ys, const uint64_t* m_dev) {
+                    uint64_t xs, uint64_t ys, const uint64_t* m_dev,
+                    const EstJob* est = nullptr) {
   NttPlan p;
   if (!ntt_make_plan(n, m, &p))
     return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
@@ -239,7 +240,8 @@ qrng_status run_ntt(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t
     W = Wt;
   }
   HIP_TRY(ntt_hash(p, reinterpret_cast<const uint32_t*>(x), n, m, W,
-                   reinterpret_cast<uint32_t*>(y), ctx->work, batch, xs, ys, ctx->tw, s, m_dev));
+                   reinterpret_cast<uint32_t*>(y), ctx->work, batch, xs, ys, ctx->tw, s, m_dev,
+                   est));
   return QRNG_OK;
 }
 
@@ -279,7 +281,8 @@ qrng_status seed_spectra(qrng_ctx* ctx, Seed& sd, uint64_t n, uint64_t m, hipStr
 // m_dev (nullable): valid output length computed on the device, <= m.
 qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
                      Seed* sd, uint64_t m, uint64_t* y, int path, hipStream_t s, int batch,
-                     uint64_t xs, uint64_t ys, const uint64_t* m_dev = nullptr) {
+                     uint64_t xs, uint64_t ys, const uint64_t* m_dev = nullptr,
+                     const EstJob* est = nullptr) {
   if (path == QRNG_PATH_AUTO) path = choose_path(n, m);
   if (path == QRNG_PATH_DIRECT) return run_direct(ctx, x, n, seed, m, y, s, batch, xs, ys, m_dev);
   if (path == QRNG_PATH_NTT) {
@@ -288,7 +291,7 @@ qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_
       qrng_status st = seed_spectra(ctx, *sd, n, m, s, &W);
       if (st) return st;
     }
-    return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys, m_dev);
+    return run_ntt(ctx, x, n, seed, W, m, y, s, batch, xs, ys, m_dev, est);
   }
   if (path == QRNG_PATH_MFMA) {
     HIP_TRY(mfma_hash(reinterpret_cast<const uint32_t*>(x), n, reinterpret_cast<const uint32_t*>(seed),
@@ -676,6 +679,14 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   a.m_cap = m_cap;
   a.out = out_dev ? (void*)out_dev : (void*)ctx->me_dev;
   a.m_out = md;
+  // on the split transform the estimate runs inside the hash's first pass
+  const int hp = path == QRNG_PATH_AUTO ? choose_path(n, m_cap) : path;
+  NttPlan pl;
+  if (hp == QRNG_PATH_NTT && ntt_make_plan(n, m_cap, &pl) && ntt_fuses_estimate(pl)) {
+    const EstJob job{samples, S, ctx->hist_scratch, a};
+    return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y,
+                    hp, s, 1, 0, 0, md, &job);
+  }
   HIP_TRY(hist_estimate(samples, S, 8, ctx->hist_scratch, nullptr, &a, s));
   return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y, path,
                   s, 1, 0, 0, md);
