@@ -289,6 +289,44 @@ def test_extract_matches_oracle(torch, ctx, cfg_k, path, cap_frac):
         ctx.unregister_seed(sid)
 
 
+@pytest.mark.parametrize("logn", [21, 22, 23])
+def test_extract_estimate_in_column_pass(torch, ctx, logn):
+    """On the split transform (columns of 2^7, 2^8, 2^9) the estimate runs in
+    extra workgroups of the first column pass, handing over through a ticket
+    that each call leaves at zero: consecutive calls with different sources,
+    a direct-path call in between, each against the oracle."""
+    n = 1 << logn
+    S = n // 8
+    sw = qi.gen_seed_words(2 * n - 1, 900 + logn)
+    sid = ctx.register_seed(dev(torch, sw), 2 * n - 1)
+    try:
+        for k, (sigma, path) in enumerate([(20.0, 2), (3.0, 2), (6.5, 1), (45.0, 2)]):
+            if path == 1 and logn > 21:
+                continue  # the direct product at these sizes only repeats the n = 2^21 case
+            log("extract n=2^%d sigma=%.1f path=%d" % (logn, sigma, path))
+            s = qi.gen_adc(S, sigma, seed=400 + 10 * logn + k)
+            ref = oracle.minentropy_counts(oracle.histogram(s, 8), 8)
+            m = oracle.output_bits(n, 8, ref["h_mod"])
+            m_out = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+            me_out = torch.zeros(128, dtype=torch.uint8, device="cuda:0")
+            y = torch.full(((n + 63) // 64,), -1, dtype=torch.int64, device="cuda:0")
+            ctx.extract(torch.from_numpy(s).to("cuda:0"), sid, n, y=y, m_out=m_out,
+                        me_out=me_out, path=path)
+            torch.cuda.synchronize()
+            me = ctx.me_result_from_bytes(me_out)
+            for key in ("mu_hat", "sigma_hat", "h_min", "h_actual", "d_u", "delta_h_m", "h_mod"):
+                assert abs(me[key] - ref[key]) <= TOL, (key, me[key], ref[key])
+            assert me["samples"] == S
+            assert int(m_out.item()) == m
+            want = ref_hash(qi.samples_as_words(s), n, sw, m)
+            got = host(y)
+            nw = (m + 63) // 64
+            assert np.array_equal(got[:nw], want)
+            assert not got[nw:].any()
+    finally:
+        ctx.unregister_seed(sid)
+
+
 def test_extract_security_term_and_given_model(torch, ctx):
     c = qi.config(0)
     s = qi.gen_adc(c["S"], 12.0, seed=31)
