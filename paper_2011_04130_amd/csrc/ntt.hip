@@ -488,7 +488,12 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   constexpr int N2 = 1 << LOG2, T = row_threads<LOG2, GPT>(), K = RP<LOG2>::K;
   static_assert(K >= 2, "rows are at least 2^5 long");
   static_assert(Geo<LOG2, K - 1>::r == 16 && Geo<LOG2, K - 1>::s == 1, "last round");
-  __shared__ uint32_t lds[N2 + N2 / 16];
+  // Two raw chunks of a hash are transformed side by side, one LDS buffer
+  // each, so every round of both rows shares one barrier (and, with two
+  // output chunks, so are the two inverse transforms).
+  constexpr bool JOINT = NX == 2 && !SEED && !IN_BITS && !OUT_BITS;
+  __shared__ uint32_t ldsb[JOINT ? 2 : 1][N2 + N2 / 16];
+  uint32_t* const lds = ldsb[0];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int row = blockIdx.x;
@@ -501,25 +506,55 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   const uint2* twf = TPT ? tw.fwd_t : tw.fwd;
   const uint2* twi = TPT ? tw.inv_t : tw.inv;
 
-  auto ld_lds_k = [&](auto kc) {
-    return [&](int g, int e) -> uint32_t {
+  auto ld_buf_k = [&](auto kc, const uint32_t* buf) {
+    return [=](int g, int e) -> uint32_t {
       using G = Geo<LOG2, decltype(kc)::value>;
       const int p0 = G::pos0(g);
-      return lds[p0 + (p0 >> 4) + e * G::SP];
+      return buf[p0 + (p0 >> 4) + e * G::SP];
     };
   };
-  auto st_lds_k = [&](auto kc) {
-    return [&](int g, int e, uint32_t v) {
+  auto st_buf_k = [&](auto kc, uint32_t* buf) {
+    return [=](int g, int e, uint32_t v) {
       using G = Geo<LOG2, decltype(kc)::value>;
       const int p0 = G::pos0(g);
-      lds[p0 + (p0 >> 4) + e * G::SP] = v;
+      buf[p0 + (p0 >> 4) + e * G::SP] = v;
     };
   };
+  auto ld_lds_k = [&](auto kc) { return ld_buf_k(kc, lds); };
+  auto st_lds_k = [&](auto kc) { return st_buf_k(kc, lds); };
   using G0 = Geo<LOG2, 0>;
   constexpr std::integral_constant<int, 0> k0{};
 
   uint32_t xs[NX][GPT][16];
-  static_for<0, NX>([&](auto cc) {
+  if constexpr (JOINT) {
+    static_for<0, NX>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const uint32_t* src = a.in + (uint64_t)(zy * NX + c) * (uint32_t)Nc + (uint64_t)row * N2;
+      auto ld0 = [&](int g, int e) -> uint32_t { return src[G0::pos0(g) + e * G0::s]; };
+      round_all<LOG2, 0, T, GPT, false, TPT>(tid, twf, ld0, st_buf_k(k0, ldsb[c]));
+    });
+    __syncthreads();
+    static_for<1, K - 1>([&](auto kc) {
+      static_for<0, NX>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        round_all<LOG2, decltype(kc)::value, T, GPT, false, TPT>(tid, twf, ld_buf_k(kc, ldsb[c]),
+                                                                 st_buf_k(kc, ldsb[c]));
+      });
+      __syncthreads();
+    });
+    static_for<0, NX>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) {
+        const int g = tid + u * T;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) xs[c][u][e] = ldsb[c][g * 17 + e];
+      }
+#pragma unroll
+      for (int u = 0; u < GPT; ++u) dft_reg<16, false>(xs[c][u]);
+    });
+    __syncthreads();
+  } else static_for<0, NX>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     const int item = SEED ? zy : zy * NX + c;
     if constexpr (IN_BITS) {
@@ -582,6 +617,62 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
     // y1 = m1 + (C-A) x0.  m1 takes x1's registers (x1 is not needed after
     // y0's products).
     const bool three = NX == 2 && a.ny == 2;
+    if constexpr (JOINT) {
+      if (three) {
+        // y0 = A (x0 + x1) + (B - A) x1 into xs[0], y1 = A (x0 + x1) + (C - A) x0
+        // into xs[1], then both inverse transforms side by side
+        const uint32_t* wrow = a.W + (uint64_t)row * N2;
+#pragma unroll
+        for (int u = 0; u < GPT; ++u) {
+          const uint32_t* wa = wrow + (tid + u * T) * 4;
+          const uint32_t* wb = wa + (uint32_t)Nc;
+          const uint32_t* wc = wb + (uint32_t)Nc;
+#pragma unroll
+          for (int e = 0; e < 16; e += 4) {
+            const uint4 va = *reinterpret_cast<const uint4*>(wa + (e / 4) * (N2 / 4));
+            const uint4 vb = *reinterpret_cast<const uint4*>(wb + (e / 4) * (N2 / 4));
+            const uint4 vc = *reinterpret_cast<const uint4*>(wc + (e / 4) * (N2 / 4));
+            const uint32_t A4[4] = {va.x, va.y, va.z, va.w};
+            const uint32_t B4[4] = {vb.x, vb.y, vb.z, vb.w};
+            const uint32_t C4[4] = {vc.x, vc.y, vc.z, vc.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t x0 = xs[0][u][e + i], x1 = xs[1][u][e + i];
+              const uint32_t mm = mul_mont(red2(x0 + x1), A4[i]);
+              xs[0][u][e + i] = red2(mm + mul_mont(x1, B4[i]));
+              xs[1][u][e + i] = red2(mm + mul_mont(x0, C4[i]));
+            }
+          }
+        }
+        static_for<0, 2>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+#pragma unroll
+          for (int u = 0; u < GPT; ++u) {
+            dft_reg<16, true>(xs[o][u]);
+            const int g = tid + u * T;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) ldsb[o][g * 17 + e] = xs[o][u][e];
+          }
+        });
+        __syncthreads();
+        static_for_down<1, K - 1>([&](auto kc) {
+          static_for<0, 2>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            round_all<LOG2, decltype(kc)::value, T, GPT, true, TPT>(
+                tid, twi, ld_buf_k(kc, ldsb[o]), st_buf_k(kc, ldsb[o]));
+          });
+          __syncthreads();
+        });
+        static_for<0, 2>([&](auto oc) {
+          constexpr int o = decltype(oc)::value;
+          uint32_t* __restrict__ dst =
+              a.out + (uint64_t)(zy * 2 + o) * (uint32_t)Nc + (uint64_t)row * N2;
+          auto st0 = [&](int g, int e, uint32_t v) { dst[G0::pos0(g) + e * G0::s] = v; };
+          round_all<LOG2, 0, T, GPT, true, TPT>(tid, twi, ld_buf_k(k0, ldsb[o]), st0);
+        });
+        return;
+      }
+    }
     for (int o = 0; o < a.ny; ++o) {
       uint32_t acc[GPT][16];
 #pragma unroll
