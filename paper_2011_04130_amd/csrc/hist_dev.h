@@ -374,16 +374,18 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
 // the next launch.  The rows are published without a device-scope release
 // fence, which would write back every dirty line of this die's L2 (the
 // other work's output streams through it): they are stored write-through
-// (device-scope atomic stores) and each thread waits for its stores to
-// complete (a workgroup-scope release) before the barrier that precedes the
-// ticket.  The last workgroup invalidates its die's caches (device-scope
-// acquire) before reading the rows.  lds: at least max(HCW * HB words,
+// (device-scope atomic stores) and each thread waits until its stores have
+// completed (s_waitcnt 0; a workgroup-scope release alone emits no wait for
+// them) before the barrier that precedes the ticket.  The last workgroup
+// invalidates its die's caches (device-scope acquire) before reading the
+// rows.  lds: at least max(HCW * HB words,
 // sizeof(FinishLds)) bytes, 16-byte aligned.
 template <int NT, int HCW>
 __device__ void estimate_workgroup(const HistArgs& a, uint32_t wg, uint32_t* ticket,
                                    uint32_t* lds) {
   hist_part_body<NT, HCW, true>(a, wg, lds);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) lds[0] = atomicAdd(ticket, 1u) == a.G - 1 ? 1u : 0u;
   __syncthreads();
