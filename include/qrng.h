@@ -153,6 +153,25 @@ qrng_status qrng_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_dev, uint
                                       uint32_t seed_id, uint64_t m, uint64_t *y_dev,
                                       int path, void *stream);
 
+/* Sec. III.D modified Toeplitz hash k = (A, I_m) x mod 2 with an (n-1)-bit
+ * seed a: A is the m x (n-m) Toeplitz block A[i][j] = a[n-m-1+i-j] (seed bit
+ * q is a_{q+1} of the paper; first row a[n-m-1] down to a[0], first column
+ * a[n-m-1] up to a[n-2]) and the identity block adds raw bit n-m+i to key bit
+ * i.  x is n raw bits, y is m bits (ceil(m/64) words, bits from m on written
+ * as 0) and must not overlap x or the seed.  0 < n; m <= n; m == 0 is a
+ * no-op; m == n gives y = x.  The product A x[0, n-m) runs on `path` like
+ * qrng_toeplitz_hash on an (n-m)-bit block (m may exceed n-m here), then one
+ * kernel adds the identity part.  Enqueued on `stream`. */
+qrng_status qrng_modified_toeplitz_hash(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
+                                        const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
+                                        int path, void *stream);
+/* As qrng_modified_toeplitz_hash with a registered seed (its first n-1 bits;
+ * the transform-domain copy is shared with ordinary hashes of the same
+ * transform length). */
+qrng_status qrng_modified_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_dev,
+                                               uint64_t n, uint32_t seed_id, uint64_t m,
+                                               uint64_t *y_dev, int path, void *stream);
+
 /* One asynchronous pass of the whole path over a block of S 8-bit samples
  * (S a multiple of 8): the histogram and the min-entropy estimate of Sec. II,
  * the output length m of Sec. III.B (whole bits per sample, minus

@@ -17,7 +17,9 @@ Generators", arXiv 2011.04130):
 * ``toeplitz_fft64`` -- the paper's own accelerated method (Sec. III.B,
   Definition 1 and Theorems 1-2): embed T in the (n+m-1)-square circulant,
   zero-pad r, k' = F^-1(F a . F r'), round, mod 2, keep k_n..k_{n+m-1}.
-* ``modified_toeplitz`` -- Sec. III.D, k = (A, I_m) r with the (n-1)-bit seed.
+* ``modified_toeplitz`` -- Sec. III.D, k = (A, I_m) r with the (n-1)-bit seed;
+  ``modified_toeplitz_packed`` the same on packed words through the
+  column split (A x_low with the C hash, plus the raw tail).
 * ``gaussian_model``, ``minentropy_dists``, ``minentropy_counts`` -- Sec. II:
   min-entropy -log2 max P, the statistical distance d_U over the set U, the
   finite-size correction Delta H_m = log2(d_U / 2^-(N+1) + 1) and
@@ -241,6 +243,26 @@ def modified_toeplitz(r_bits: np.ndarray, a_bits: np.ndarray, m: int) -> np.ndar
         acc ^= int(r[w + i])
         k[i] = acc
     return k
+
+
+def modified_toeplitz_packed(x_words: np.ndarray, n: int, a_words: np.ndarray,
+                             m: int) -> np.ndarray:
+    """Sec. III.D on packed words, ceil(m/64) uint64 words (tail zero).
+
+    The columns of (A, I_m) split the product: A times the first n-m raw bits
+    is the Sec. III.B hash of an (n-m)-bit block with the same seed (A[i, j] =
+    a[n-m-1+i-j], 0-indexed, is T[i][j] = s[n'-1+i-j] with n' = n-m), and I_m
+    adds raw bits n-m .. n-1.  ``modified_toeplitz`` (the product written out)
+    pins this route.
+    """
+    w = n - m
+    assert 0 <= m <= n
+    if w > 0:
+        y = toeplitz_packed(x_words, w, a_words, m)
+    else:
+        y = np.zeros((m + 63) // 64, dtype=np.uint64)
+    tail = pack_bits(unpack_bits(x_words, n)[w:n])
+    return (y ^ tail[: len(y)]).astype(np.uint64)
 
 
 # ---------------------------------------------------------------------------

@@ -155,6 +155,35 @@ class Context:
                                                   _stream(torch, self.device, stream)))
         return y
 
+    def modified_hash(self, x, n: int, seed, m: int, y=None, path: int = PATH_AUTO,
+                      stream=None):
+        """Sec. III.D: y = (A, I_m) x mod 2 with an (n-1)-bit seed (returns y)."""
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        sp = self._dev_tensor(seed, "seed")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        if seed.numel() * seed.element_size() < _words(max(n - 1, 1)) * 8:
+            raise ValueError("seed holds fewer than n-1 bits")
+        y = self._out(y, m)
+        yp = self._dev_tensor(y, "y")
+        check(self._lib.qrng_modified_toeplitz_hash(self._h, xp, n, sp, m, yp, path,
+                                                    _stream(torch, self.device, stream)))
+        return y
+
+    def modified_hash_seeded(self, x, n: int, seed_id: int, m: int, y=None,
+                             path: int = PATH_AUTO, stream=None):
+        """modified_hash with a registered seed (its first n-1 bits)."""
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        y = self._out(y, m)
+        yp = self._dev_tensor(y, "y")
+        check(self._lib.qrng_modified_toeplitz_hash_seeded(self._h, xp, n, seed_id, m, yp, path,
+                                                           _stream(torch, self.device, stream)))
+        return y
+
     def extract(self, samples, seed_id: int, m_cap: int, y=None, m_out=None, me_out=None,
                 model: int = MODEL_FIT, mu: float = 0.0, sigma: float = 0.0,
                 u_mode: int = U_MODEL_ARGMAX, log2_inv_eps: float = 0.0,

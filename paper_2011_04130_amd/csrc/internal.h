@@ -132,6 +132,12 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
                        hipStream_t s, int batch, uint64_t x_stride_bits,
                        uint64_t y_stride_bits, const uint64_t* m_dev = nullptr);
 
+// ------------------------------------------------- modified Toeplitz tail
+// y (ceil(m/64) words) ^= raw bits off .. off+m-1 of x (n bits), or = them
+// with `assign`; bits from m on are written as 0.
+hipError_t xor_tail_bits(const uint64_t* x, uint64_t n, uint64_t off, uint64_t m, uint64_t* y,
+                         bool assign, hipStream_t s);
+
 // -------------------------------------------------------------- MFMA path
 // `batch` blocks sharing one seed as one int8 matrix product (strides as in
 // ntt_hash).  No workspace.

@@ -926,7 +926,8 @@ void build_tw_tables(uint2* fwd, uint2* inv, uint32_t* g_lo, uint32_t* g_hi) {
 }
 
 bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* p) {
-  if (n == 0 || m == 0 || m > n || n >= P) return false;
+  // row sums are at most n < p; m may exceed n (the modified Toeplitz block)
+  if (n == 0 || m == 0 || n >= P) return false;
   const uint64_t L = n + m - 1;
   if (L <= (1ull << LOG_MAX)) {
     p->log_nc = ceil_log2(L) < 10 ? 10 : ceil_log2(L);

@@ -301,6 +301,37 @@ qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_
   return fail(QRNG_EUNSUPPORTED, "path %d is not available for this call", path);
 }
 
+// Sec. III.D: the (n-m)-column Toeplitz product with the same seed, then the
+// identity block's raw bits n-m .. n-1 added to the key.
+qrng_status modified_hash(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_t* seed,
+                          Seed* sd, uint64_t m, uint64_t* y, int path, hipStream_t s) {
+  const uint64_t w = n - m;
+  if (w > 0) {
+    qrng_status st = hash_one(ctx, x, w, seed, sd, m, y, path, s, 1, 0, 0);
+    if (st) return st;
+  }
+  HIP_TRY(xor_tail_bits(x, n, w, m, y, w == 0, s));
+  return QRNG_OK;
+}
+
+qrng_status check_modified_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                const uint64_t* seed, uint64_t m, const uint64_t* y, int path) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  if (!x || !seed || !y) return fail(QRNG_EINVAL, "null buffer");
+  if (!aligned8(x) || !aligned8(seed) || !aligned8(y))
+    return fail(QRNG_EINVAL, "buffers must be 8-byte aligned");
+  if (n == 0) return fail(QRNG_EINVAL, "n must be positive");
+  if (m > n) return fail(QRNG_EINVAL, "m (%llu) exceeds n (%llu)", (unsigned long long)m,
+                         (unsigned long long)n);
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  if (m == 0) return QRNG_OK;
+  if (overlap(y, words64(m) * 8, x, words64(n) * 8))
+    return fail(QRNG_EINVAL, "output overlaps the raw block");
+  if (n > 1 && overlap(y, words64(m) * 8, seed, words64(n - 1) * 8))
+    return fail(QRNG_EINVAL, "output overlaps the seed");
+  return QRNG_OK;
+}
+
 double phi(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
 
 constexpr double kTieRel = 1e-9;  // relative closeness treated as a tie of model bins
@@ -613,6 +644,35 @@ qrng_status qrng_seed_unregister(qrng_ctx* ctx, uint32_t seed_id) {
   for (auto& sp : it->second.spectra) (void)hipFree(sp.second);
   ctx->seeds.erase(it);
   return QRNG_OK;
+}
+
+qrng_status qrng_modified_toeplitz_hash(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                        const uint64_t* seed, uint64_t m, uint64_t* y, int path,
+                                        void* stream) {
+  qrng_status st = check_modified_args(ctx, x, n, seed, m, y, path);
+  if (st || m == 0) return st;
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  return modified_hash(ctx, x, n, seed, nullptr, m, y, path,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+qrng_status qrng_modified_toeplitz_hash_seeded(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                               uint32_t seed_id, uint64_t m, uint64_t* y,
+                                               int path, void* stream) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  auto it = ctx->seeds.find(seed_id);
+  if (it == ctx->seeds.end()) return fail(QRNG_EINVAL, "unknown seed id %u", seed_id);
+  Seed& sd = it->second;
+  qrng_status st = check_modified_args(ctx, x, n, sd.ptr, m, y, path);
+  if (st || m == 0) return st;
+  if (n - 1 > sd.L)
+    return fail(QRNG_EINVAL, "seed has %llu bits, the modified hash needs %llu",
+                (unsigned long long)sd.L, (unsigned long long)(n - 1));
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  return modified_hash(ctx, x, n, sd.ptr, &sd, m, y, path,
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 qrng_status qrng_toeplitz_hash_seeded(qrng_ctx* ctx, const uint64_t* x, uint64_t n,

@@ -213,3 +213,38 @@ def test_modified_toeplitz_text_formula():
         rp = np.concatenate([r[:w], np.zeros(m, np.uint8)])
         kp = gf2_matvec(oracle.circulant_matrix(ap, n), rp)
         assert np.array_equal(kp[w - 1: w - 1 + m] ^ r[w:], want)
+
+
+def test_modified_toeplitz_packed_matches_definition():
+    # the packed column-split route against the product written out, including
+    # m > n - m (more key bits than A has columns), m = n (k = r), m = 1 and
+    # lengths that are not multiples of 64
+    rng = np.random.default_rng(23)
+    for n, m in [(1, 1), (2, 1), (9, 9), (64, 40), (65, 64), (100, 1), (130, 97), (200, 150),
+                 (257, 100), (300, 299)]:
+        a = rand_bits(max(n - 1, 1), rng)
+        r = rand_bits(n, rng)
+        want = oracle.pack_bits(oracle.modified_toeplitz(r, a, m))
+        got = oracle.modified_toeplitz_packed(oracle.pack_bits(r), n, oracle.pack_bits(a), m)
+        assert np.array_equal(got, want), (n, m)
+        if m == n:
+            assert np.array_equal(got, oracle.pack_bits(r))
+
+
+def test_modified_toeplitz_columns():
+    # unit raw vectors read the columns of (A, I_m): e_j (j < n-m) gives
+    # A[:, j] = a[n-m-1+i-j], e_{n-m+i} gives key bit i alone
+    rng = np.random.default_rng(24)
+    n, m = 40, 25
+    a = rand_bits(n - 1, rng)
+    w = n - m
+    for j in range(n):
+        r = np.zeros(n, np.uint8)
+        r[j] = 1
+        k = oracle.modified_toeplitz(r, a, m)
+        if j < w:
+            assert np.array_equal(k, np.array([a[w - 1 + i - j] for i in range(m)], np.uint8))
+        else:
+            e = np.zeros(m, np.uint8)
+            e[j - w] = 1
+            assert np.array_equal(k, e)
