@@ -267,6 +267,42 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
     return out
 
 
+def bench_modified(ctx, q, torch, qi, reps=30):
+    """Sec. III.D against Sec. III.B on the n = 2^23 workload block at its
+    m = 5n/8: the ordinary hash (seed n+m-1 bits, split 2^23-point transform)
+    and the modified hash (seed n-1 bits: the (n-m)-column product fits one
+    2^23-point transform, plus the identity block's raw tail), both with a
+    registered seed on the NTT path; hash only, raw Gbit/s."""
+    cfg = qi.config(1)
+    n, m = cfg["n"], cfg["m_expected"]
+    xw = qi.samples_as_words(qi.gen_adc(cfg["S"], cfg["sigma"], seed=cfg["adc_seed"]))
+    x = _dev_words(torch, xw)
+    y = torch.empty((m + 63) // 64, dtype=torch.int64, device="cuda:0")
+    sid_t = ctx.register_seed(_dev_words(torch, qi.gen_seed_words(n + m - 1, cfg["seed_seed"])),
+                              n + m - 1)
+    sid_m = ctx.register_seed(_dev_words(torch, qi.gen_seed_words(n - 1, cfg["seed_seed"])),
+                              n - 1)
+    res = {"workload": cfg["name"], "n": n, "m": m,
+           "seed_bits": {"toeplitz": n + m - 1, "modified": n - 1}}
+    for name, fn in (("toeplitz", lambda: ctx.hash_seeded(x, n, sid_t, m, y=y, path=q.PATH_NTT)),
+                     ("modified", lambda: ctx.modified_hash_seeded(x, n, sid_m, m, y=y,
+                                                                   path=q.PATH_NTT))):
+        t = _time_fn(torch, fn, reps)
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        pr = ctx.profile_read()
+        ctx.profile(False)
+        res[name] = {"raw_gbps": round(n / t / 1e9, 3), "ms": round(t * 1e3, 4),
+                     "kernels_us": {k: round(ms / c * 1e3, 1) for k, (c, ms) in pr.items()}}
+    res["modified_vs_toeplitz"] = round(res["modified"]["raw_gbps"] / res["toeplitz"]["raw_gbps"], 3)
+    ctx.unregister_seed(sid_t)
+    ctx.unregister_seed(sid_m)
+    return res
+
+
 def bench_sweep(ctx, q, torch, qi, reps=3):
     """A 2^30-bit raw sequence (2^27 ADC samples) cut into blocks of n = 2^12
     .. 2^24 bits, every block hashed with one seed at m = 5n/8; raw Gbit/s per
@@ -402,7 +438,9 @@ def main():
     ap.add_argument("--uneven", type=int, default=1, help="also time the 4096-block uneven plan")
     ap.add_argument("--sweep", type=int, default=1, help="also time the block-length sweep")
     ap.add_argument("--serve", type=int, default=1, help="also run the serving-loop latency test")
-    ap.add_argument("--only", choices=["uneven", "sweep", "serve"],
+    ap.add_argument("--modified", type=int, default=1,
+                    help="also time the modified Toeplitz hash against the ordinary one")
+    ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified"],
                     help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
@@ -430,7 +468,8 @@ def main():
 
     if args.only:
         ctx = q.Context(0)
-        fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve}[args.only]
+        fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve,
+              "modified": bench_modified}[args.only]
         print(json.dumps(fn(ctx, q, torch, qi)))
         ctx.close()
         return
@@ -564,6 +603,8 @@ def main():
         out["sweep_2^30"]["best_raw_vs_plain"] = {
             k: round(max(v for kk, v in row.items() if isinstance(v, float)) / plain, 3)
             for k, row in out["sweep_2^30"]["by_block_bits"].items()}
+    if args.modified:
+        out["modified_toeplitz"] = bench_modified(ctx, q, torch, qi)
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:

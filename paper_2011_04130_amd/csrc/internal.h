@@ -22,6 +22,7 @@ enum KernelId {
   KID_DIRECT_PREP,    // output clear and raw-block reversal
   KID_HIST,           // sample histogram
   KID_MFMA,           // int8 matrix-core product
+  KID_MOD_TAIL,       // identity block of the modified Toeplitz hash
   KID_COUNT
 };
 const char* kernel_name(int kid);

@@ -33,8 +33,10 @@ hipError_t xor_tail_bits(const uint64_t* x, uint64_t n, uint64_t off, uint64_t m
                          bool assign, hipStream_t s) {
   if (m == 0) return hipSuccess;
   const uint64_t nw = (m + 63) / 64;
+  prof_begin(KID_MOD_TAIL, s);
   hipLaunchKernelGGL(k_xor_tail, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, x,
                      (n + 63) / 64, off, m, y, assign ? 1 : 0);
+  prof_end(KID_MOD_TAIL, s);
   return hipGetLastError();
 }
 

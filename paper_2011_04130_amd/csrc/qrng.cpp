@@ -28,7 +28,7 @@ const char* kernel_name(int kid) {
   static const char* names[KID_COUNT] = {"ntt_cols_fwd", "ntt_rows_hash", "ntt_rows_seed",
                                          "ntt_cols_inv", "ntt_fused_hash", "ntt_fused_seed",
                                          "direct",       "direct_prep",   "histogram",
-                                         "mfma"};
+                                         "mfma",         "modified_tail"};
   return (kid >= 0 && kid < KID_COUNT) ? names[kid] : nullptr;
 }
 }  // namespace qrng
