@@ -153,6 +153,21 @@ qrng_status qrng_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_dev, uint
                                       uint32_t seed_id, uint64_t m, uint64_t *y_dev,
                                       int path, void *stream);
 
+/* The paper's own accelerated method (Sec. III.B, Definition 1 and Theorems
+ * 1-2) in float64, for comparison with the exact paths: the seed's n+m-1 bits
+ * and the raw block zero-padded to a power-of-two length N >= n+m-1 are
+ * transformed together (one complex transform, the two real spectra
+ * separated), multiplied, transformed back; the kept rows n-1 .. n+m-2 are
+ * divided by N, rounded to the nearest integer and reduced mod 2.  Same
+ * arguments and output as qrng_toeplitz_hash; n+m-1 <= 2^26; workspace of
+ * 32 N bytes in the context.  max_err_dev (nullable, device double) receives
+ * the largest distance of a kept value from its integer: the bits equal the
+ * exact hash while it stays below 1/2 (it is about 1e-9 at N = 2^24).
+ * Enqueued on `stream`. */
+qrng_status qrng_toeplitz_hash_fft64(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
+                                     const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
+                                     double *max_err_dev, void *stream);
+
 /* Sec. III.D modified Toeplitz hash k = (A, I_m) x mod 2 with an (n-1)-bit
  * seed a: A is the m x (n-m) Toeplitz block A[i][j] = a[n-m-1+i-j] (seed bit
  * q is a_{q+1} of the paper; first row a[n-m-1] down to a[0], first column

@@ -89,6 +89,7 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
            "qrng_modified_toeplitz_hash", "qrng_modified_toeplitz_hash_seeded",
+           "qrng_toeplitz_hash_fft64",
            "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
            "qrng_plan_create", "qrng_plan_execute", "qrng_plan_query", "qrng_plan_destroy",
            "qrng_tune_export", "qrng_tune_import",
@@ -131,6 +132,8 @@ def load_library(path: str | None = None):
     lib.qrng_seed_unregister.restype = i32
     lib.qrng_toeplitz_hash_seeded.argtypes = [vp, vp, u64, u32, u64, vp, i32, vp]
     lib.qrng_toeplitz_hash_seeded.restype = i32
+    lib.qrng_toeplitz_hash_fft64.argtypes = [vp, vp, u64, vp, u64, vp, vp, vp]
+    lib.qrng_toeplitz_hash_fft64.restype = i32
     lib.qrng_modified_toeplitz_hash.argtypes = [vp, vp, u64, vp, u64, vp, i32, vp]
     lib.qrng_modified_toeplitz_hash.restype = i32
     lib.qrng_modified_toeplitz_hash_seeded.argtypes = [vp, vp, u64, u32, u64, vp, i32, vp]

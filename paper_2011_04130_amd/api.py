@@ -155,6 +155,25 @@ class Context:
                                                   _stream(torch, self.device, stream)))
         return y
 
+    def hash_fft64(self, x, n: int, seed, m: int, y=None, err_out=None, stream=None):
+        """The paper's float64 circulant method on the device (returns y).
+
+        err_out: float64 tensor of >= 1 element (receives the largest distance
+        of a kept value from its integer)."""
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        sp = self._dev_tensor(seed, "seed")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        if m and seed.numel() * seed.element_size() < _words(n + m - 1) * 8:
+            raise ValueError("seed holds fewer than n+m-1 bits")
+        y = self._out(y, m)
+        yp = self._dev_tensor(y, "y")
+        ep = self._dev_tensor(err_out, "err_out") if err_out is not None else None
+        check(self._lib.qrng_toeplitz_hash_fft64(self._h, xp, n, sp, m, yp, ep,
+                                                 _stream(torch, self.device, stream)))
+        return y
+
     def modified_hash(self, x, n: int, seed, m: int, y=None, path: int = PATH_AUTO,
                       stream=None):
         """Sec. III.D: y = (A, I_m) x mod 2 with an (n-1)-bit seed (returns y)."""

@@ -19,8 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libqrng.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["ntt.hip", "direct.hip", "hist.hip", "mfma.hip", "modified.hip", "qrng.cpp",
-           "server.cpp"]
+SOURCES = ["ntt.hip", "direct.hip", "hist.hip", "mfma.hip", "modified.hip", "fft64.hip",
+           "qrng.cpp", "server.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -1,0 +1,246 @@
+// The paper's own accelerated method on the GPU (Sec. III.B: the circulant
+// embedding of Definition 1, diagonalised by the DFT as in Theorems 1-2),
+// in float64 as the paper computes it: k' = F^-1(F a . F r') with a the
+// n+m-1 seed bits and r' the raw block zero-padded, both to a power-of-two
+// length N >= n+m-1 (the kept rows never wrap, so padding leaves them
+// unchanged); then round, mod 2, and keep rows n-1 .. n+m-2.  A comparison
+// path beside the exact transform mod p: it is exact only while every kept
+// value lies well within 1/2 of an integer, and it reports the largest
+// distance it saw.
+//
+// Both real inputs share one complex transform (z = a + i r; the two spectra
+// are separated from Z[k] and conj Z[N-k]), so a hash costs one forward and
+// one inverse complex transform of length N plus two elementwise passes.
+// Transforms are Stockham autosort passes (no bit reversal), radix 16 with
+// a radix 2/4/8 pass first when log2 N is not a multiple of 4, one 16-point
+// DFT in registers per thread, twiddles from sincospi.
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace qrng {
+
+namespace {
+
+struct cplx {
+  double x, y;
+};
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
+}
+
+// cos and sin of 2 pi k / 16, k = 0..4 (the rest follow by symmetry)
+constexpr double C16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                           0.38268343236508977173, 0.0};
+
+// exp(sign 2 pi i e / 16), sign = -1 forward, +1 inverse
+template <bool INV>
+__device__ __forceinline__ cplx root16(int e) {
+  e &= 15;
+  // cos(2 pi e/16) and sin(2 pi e/16) from the first quadrant
+  const int q = e >> 2, r = e & 3;
+  double c, s;
+  if (q == 0) {
+    c = C16[r];
+    s = C16[4 - r];
+  } else if (q == 1) {
+    c = -C16[4 - r];
+    s = C16[r];
+  } else if (q == 2) {
+    c = -C16[r];
+    s = -C16[4 - r];
+  } else {
+    c = C16[4 - r];
+    s = -C16[r];
+  }
+  return {c, INV ? s : -s};
+}
+
+constexpr int ilg(int v) { return v <= 1 ? 0 : 1 + ilg(v >> 1); }
+constexpr int brv(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register R-point DFT (R = 2, 4, 8, 16), natural order in and out:
+// v[k] = sum_q v[q] exp(sign 2 pi i q k / R); radix-2 decimation in time on
+// the bit-reversed input.
+template <int R, bool INV>
+__device__ __forceinline__ void dft_small(cplx (&v)[R]) {
+  constexpr int LG = ilg(R);
+  cplx t[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) t[i] = v[brv(i, LG)];
+#pragma unroll
+  for (int half = 1; half < R; half *= 2) {
+#pragma unroll
+    for (int base = 0; base < R; base += 2 * half) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const cplx w = root16<INV>(j * (16 / (2 * half)));
+        const cplx b = j == 0 ? t[base + j + half] : cmul(t[base + j + half], w);
+        const cplx a = t[base + j];
+        t[base + j] = cadd(a, b);
+        t[base + j + half] = csub(a, b);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = t[i];
+}
+
+// z[q] = (seed bit q, raw bit q) for q < N (0 past L and n); clears *err.
+__global__ __launch_bounds__(256) void k_fft_pack(const uint32_t* __restrict__ seed, uint64_t L,
+                                                  const uint32_t* __restrict__ x, uint64_t n,
+                                                  cplx* __restrict__ z, uint64_t N,
+                                                  unsigned long long* err) {
+  const uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q == 0 && err) *err = 0ull;
+  if (q >= N) return;
+  const double a = q < L ? (double)((seed[q >> 5] >> (q & 31)) & 1u) : 0.0;
+  const double r = q < n ? (double)((x[q >> 5] >> (q & 31)) & 1u) : 0.0;
+  z[q] = {a, r};
+}
+
+// One Stockham pass of radix R over N points: sub-transforms of length Ns
+// are done; thread j combines R of them (inputs j + r N/R) into one of
+// length Ns R at (j / Ns) Ns R + j mod Ns + r Ns.
+template <int R, bool INV>
+__global__ __launch_bounds__(256) void k_fft_pass(const cplx* __restrict__ in,
+                                                  cplx* __restrict__ out, uint64_t N,
+                                                  uint64_t Ns) {
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t stride = N / R;
+  if (j >= stride) return;
+  cplx v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = in[j + r * stride];
+  const uint64_t k = j % Ns;
+  if (Ns > 1) {
+    // twiddle exp(sign 2 pi i r k / (Ns R)) = sincospi(sign 2 r k / (Ns R))
+    const double base = (INV ? 2.0 : -2.0) * (double)k / (double)(Ns * R);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      double s, c;
+      sincospi(base * r, &s, &c);
+      v[r] = cmul(v[r], cplx{c, s});
+    }
+  }
+  dft_small<R, INV>(v);
+  const uint64_t o = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+}
+
+// Separate the two real inputs' spectra from Z = F(a + i r) and multiply:
+// A[k] = (Z[k] + conj Z[-k]) / 2, R[k] = (Z[k] - conj Z[-k]) / (2i).  Thread
+// k <= N/2 writes P[k] and P[N-k] in place.
+__global__ __launch_bounds__(256) void k_fft_product(cplx* __restrict__ Z, uint64_t N) {
+  const uint64_t k = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k > N / 2) return;
+  const uint64_t kk = (N - k) & (N - 1);
+  const cplx zk = Z[k], zc = Z[kk];
+  auto prod = [](cplx p, cplx q) {  // p = Z[k], q = Z[-k]
+    const cplx a = {0.5 * (p.x + q.x), 0.5 * (p.y - q.y)};
+    const cplx r = {0.5 * (p.y + q.y), -0.5 * (p.x - q.x)};
+    return cmul(a, r);
+  };
+  const cplx pk = prod(zk, zc);
+  const cplx pc = prod(zc, zk);
+  Z[k] = pk;
+  if (kk != k) Z[kk] = pc;
+}
+
+// Rows t = n-1+i, i < m: v = Re(k'[t]) / N, bit i = rint(v) & 1, packed with
+// wave ballots (64 rows per word); bits from m on are 0.  *err = the largest
+// |v - rint(v)| as the bits of a non-negative double.
+__global__ __launch_bounds__(256) void k_fft_bits(const cplx* __restrict__ K, uint64_t N,
+                                                  uint64_t n, uint64_t m,
+                                                  uint64_t* __restrict__ y,
+                                                  unsigned long long* err) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t words = (m + 63) / 64;
+  uint32_t bit = 0;
+  double d = 0.0;
+  if (i < m) {
+    const double v = K[n - 1 + i].x / (double)N;
+    const double rv = rint(v);
+    bit = (uint32_t)((long long)rv & 1);
+    d = fabs(v - rv);
+  }
+  const uint64_t bal = __ballot(bit);
+  if ((threadIdx.x & 63) == 0 && (i >> 6) < words) y[i >> 6] = bal;
+  for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+  if (err && (threadIdx.x & 63) == 0 && d > 0.0)
+    atomicMax(err, (unsigned long long)__double_as_longlong(d));
+}
+
+template <bool INV>
+hipError_t transform(cplx* a, cplx* b, uint64_t N, hipStream_t s, cplx** result) {
+  int log = 0;
+  while ((1ull << log) < N) ++log;
+  cplx* in = a;
+  cplx* out = b;
+  uint64_t Ns = 1;
+  auto pass = [&](int R) {
+    const uint64_t threads = N / (uint64_t)R;
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    switch (R) {
+      case 2: hipLaunchKernelGGL((k_fft_pass<2, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
+      case 4: hipLaunchKernelGGL((k_fft_pass<4, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
+      case 8: hipLaunchKernelGGL((k_fft_pass<8, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
+      default: hipLaunchKernelGGL((k_fft_pass<16, INV>), grid, dim3(256), 0, s, in, out, N, Ns);
+    }
+    Ns *= (uint64_t)R;
+    cplx* t = in;
+    in = out;
+    out = t;
+  };
+  if (log % 4) pass(1 << (log % 4));
+  for (int p = 0; p < log / 4; ++p) pass(16);
+  *result = in;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+uint64_t fft64_length(uint64_t n, uint64_t m) {
+  const uint64_t L = n + m - 1;
+  uint64_t N = 16;
+  while (N < L) N <<= 1;
+  return N;
+}
+
+uint64_t fft64_work_words(uint64_t n, uint64_t m) { return 8 * fft64_length(n, m); }
+
+hipError_t fft64_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits, uint64_t m,
+                      uint64_t* y, unsigned long long* err, uint32_t* work, hipStream_t s) {
+  const uint64_t N = fft64_length(n, m);
+  if (N > FFT64_MAX_LENGTH) return hipErrorInvalidValue;
+  cplx* A = reinterpret_cast<cplx*>(work);
+  cplx* B = A + N;
+  const dim3 g((unsigned)((N + 255) / 256));
+  prof_begin(KID_FFT64, s);
+  hipLaunchKernelGGL(k_fft_pack, g, dim3(256), 0, s, seed_bits, n + m - 1, x_bits, n, A, N, err);
+  cplx* Z = nullptr;
+  hipError_t e = transform<false>(A, B, N, s, &Z);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fft_product, dim3((unsigned)((N / 2 + 1 + 255) / 256)), dim3(256), 0, s,
+                       Z, N);
+    cplx* other = Z == A ? B : A;
+    cplx* K = nullptr;
+    e = transform<true>(Z, other, N, s, &K);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(k_fft_bits, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, K, N, n,
+                         m, y, err);
+  }
+  prof_end(KID_FFT64, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace qrng

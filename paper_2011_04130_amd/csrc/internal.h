@@ -23,6 +23,7 @@ enum KernelId {
   KID_HIST,           // sample histogram
   KID_MFMA,           // int8 matrix-core product
   KID_MOD_TAIL,       // identity block of the modified Toeplitz hash
+  KID_FFT64,          // the paper's float64 method (all its launches)
   KID_COUNT
 };
 const char* kernel_name(int kid);
@@ -138,6 +139,18 @@ hipError_t direct_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_
 // with `assign`; bits from m on are written as 0.
 hipError_t xor_tail_bits(const uint64_t* x, uint64_t n, uint64_t off, uint64_t m, uint64_t* y,
                          bool assign, hipStream_t s);
+
+// ------------------------------------------------- float64 FFT (comparison)
+// The paper's circulant method in float64 at the power-of-two length
+// fft64_length(n, m) >= n+m-1 (at most FFT64_MAX_LENGTH); workspace
+// fft64_work_words uint32 words (two complex arrays); err (nullable, device)
+// receives the largest distance of a kept value from its integer, as the
+// bits of a double.
+constexpr uint64_t FFT64_MAX_LENGTH = 1ull << 26;
+uint64_t fft64_length(uint64_t n, uint64_t m);
+uint64_t fft64_work_words(uint64_t n, uint64_t m);
+hipError_t fft64_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits, uint64_t m,
+                      uint64_t* y, unsigned long long* err, uint32_t* work, hipStream_t s);
 
 // -------------------------------------------------------------- MFMA path
 // `batch` blocks sharing one seed as one int8 matrix product (strides as in

@@ -28,7 +28,7 @@ const char* kernel_name(int kid) {
   static const char* names[KID_COUNT] = {"ntt_cols_fwd", "ntt_rows_hash", "ntt_rows_seed",
                                          "ntt_cols_inv", "ntt_fused_hash", "ntt_fused_seed",
                                          "direct",       "direct_prep",   "histogram",
-                                         "mfma",         "modified_tail"};
+                                         "mfma",         "modified_tail", "fft64"};
   return (kid >= 0 && kid < KID_COUNT) ? names[kid] : nullptr;
 }
 }  // namespace qrng
@@ -643,6 +643,26 @@ qrng_status qrng_seed_unregister(qrng_ctx* ctx, uint32_t seed_id) {
   if (!it->second.spectra.empty()) HIP_TRY(hipDeviceSynchronize());
   for (auto& sp : it->second.spectra) (void)hipFree(sp.second);
   ctx->seeds.erase(it);
+  return QRNG_OK;
+}
+
+qrng_status qrng_toeplitz_hash_fft64(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                     const uint64_t* seed, uint64_t m, uint64_t* y,
+                                     double* max_err_dev, void* stream) {
+  qrng_status st = check_hash_args(ctx, x, n, seed, m, y, QRNG_PATH_AUTO);
+  if (st || m == 0) return st;
+  if (max_err_dev && !aligned8(max_err_dev))
+    return fail(QRNG_EINVAL, "buffers must be 8-byte aligned");
+  if (fft64_length(n, m) > FFT64_MAX_LENGTH)
+    return fail(QRNG_EINVAL, "float64 method: n + m - 1 must be at most 2^26");
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  st = ensure_work(ctx, fft64_work_words(n, m));
+  if (st) return st;
+  HIP_TRY(fft64_hash(reinterpret_cast<const uint32_t*>(x), n,
+                     reinterpret_cast<const uint32_t*>(seed), m, y,
+                     reinterpret_cast<unsigned long long*>(max_err_dev), ctx->work,
+                     reinterpret_cast<hipStream_t>(stream)));
   return QRNG_OK;
 }
 
