@@ -303,6 +303,47 @@ def bench_modified(ctx, q, torch, qi, reps=30):
     return res
 
 
+def fft64_stream_bytes(n, m):
+    """HBM bytes the float64 method streams per hash: the pack pass writes N
+    complex doubles; each Stockham pass reads and writes N (radix 16, plus a
+    radix 2/4/8 pass when log2 N is not a multiple of 4), for the forward and
+    the inverse transform; the product reads and writes N; the rounding pass
+    reads m and writes m/8."""
+    L = n + m - 1
+    N = 16
+    while N < L:
+        N <<= 1
+    lg = N.bit_length() - 1
+    passes = lg // 4 + (1 if lg % 4 else 0)
+    c = 16
+    return N, 16 * N + 2 * passes * 2 * c * N + 2 * c * N + c * m + m // 8
+
+
+def bench_fft64(ctx, q, torch, qi, reps=10):
+    """The paper's float64 circulant method on the GPU against the exact NTT
+    path, on the n = 2^23 workload block at m = 5n/8 (hash only; the NTT with
+    the seed transformed every call, as the float64 method does)."""
+    cfg = qi.config(1)
+    n, m = cfg["n"], cfg["m_expected"]
+    xw = qi.samples_as_words(qi.gen_adc(cfg["S"], cfg["sigma"], seed=cfg["adc_seed"]))
+    x = _dev_words(torch, xw)
+    sd = _dev_words(torch, qi.gen_seed_words(n + m - 1, cfg["seed_seed"]))
+    y = torch.empty((m + 63) // 64, dtype=torch.int64, device="cuda:0")
+    err = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    t_f = _time_fn(torch, lambda: ctx.hash_fft64(x, n, sd, m, y=y, err_out=err), reps)
+    t_n = _time_fn(torch, lambda: ctx.hash(x, n, sd, m, y=y, path=q.PATH_NTT), reps)
+    N, b = fft64_stream_bytes(n, m)
+    return {"workload": cfg["name"], "n": n, "m": m, "transform_length": N,
+            "fft64_raw_gbps": round(n / t_f / 1e9, 3), "fft64_ms": round(t_f * 1e3, 4),
+            "max_rounding_distance": float(err.item()),
+            "ntt_seed_each_call_raw_gbps": round(n / t_n / 1e9, 3),
+            "ntt_vs_fft64": round(t_f / t_n, 3),
+            "fft64_roofline": {"bound": "hbm", "achieved": round(b / t_f / 1e9, 1),
+                               "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                               "frac": round(b / t_f / PEAK_HBM, 4),
+                               "note": "streamed bytes of all its passes over the whole call"}}
+
+
 def bench_sweep(ctx, q, torch, qi, reps=3):
     """A 2^30-bit raw sequence (2^27 ADC samples) cut into blocks of n = 2^12
     .. 2^24 bits, every block hashed with one seed at m = 5n/8; raw Gbit/s per
@@ -440,7 +481,9 @@ def main():
     ap.add_argument("--serve", type=int, default=1, help="also run the serving-loop latency test")
     ap.add_argument("--modified", type=int, default=1,
                     help="also time the modified Toeplitz hash against the ordinary one")
-    ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified"],
+    ap.add_argument("--fft64", type=int, default=1,
+                    help="also time the paper's float64 method against the NTT path")
+    ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified", "fft64"],
                     help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
@@ -469,7 +512,7 @@ def main():
     if args.only:
         ctx = q.Context(0)
         fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve,
-              "modified": bench_modified}[args.only]
+              "modified": bench_modified, "fft64": bench_fft64}[args.only]
         print(json.dumps(fn(ctx, q, torch, qi)))
         ctx.close()
         return
@@ -605,6 +648,8 @@ def main():
             for k, row in out["sweep_2^30"]["by_block_bits"].items()}
     if args.modified:
         out["modified_toeplitz"] = bench_modified(ctx, q, torch, qi)
+    if args.fft64:
+        out["paper_method_fft64"] = bench_fft64(ctx, q, torch, qi)
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:

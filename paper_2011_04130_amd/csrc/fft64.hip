@@ -157,11 +157,14 @@ __global__ __launch_bounds__(256) void k_fft_product(cplx* __restrict__ Z, uint6
 
 // Rows t = n-1+i, i < m: v = Re(k'[t]) / N, bit i = rint(v) & 1, packed with
 // wave ballots (64 rows per word); bits from m on are 0.  *err = the largest
-// |v - rint(v)| as the bits of a non-negative double.
+// |v - rint(v)| as the bits of a non-negative double: one atomic per
+// workgroup at most, and none when the value already there is as large (a
+// single address takes every atomic, so they are kept rare).
 __global__ __launch_bounds__(256) void k_fft_bits(const cplx* __restrict__ K, uint64_t N,
                                                   uint64_t n, uint64_t m,
                                                   uint64_t* __restrict__ y,
                                                   unsigned long long* err) {
+  __shared__ double wmax[4];
   const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   const uint64_t words = (m + 63) / 64;
   uint32_t bit = 0;
@@ -174,9 +177,16 @@ __global__ __launch_bounds__(256) void k_fft_bits(const cplx* __restrict__ K, ui
   }
   const uint64_t bal = __ballot(bit);
   if ((threadIdx.x & 63) == 0 && (i >> 6) < words) y[i >> 6] = bal;
+  if (!err) return;
   for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
-  if (err && (threadIdx.x & 63) == 0 && d > 0.0)
-    atomicMax(err, (unsigned long long)__double_as_longlong(d));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    const unsigned long long bb = (unsigned long long)__double_as_longlong(b);
+    if (b > 0.0 && bb > __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(err, bb);
+  }
 }
 
 template <bool INV>
