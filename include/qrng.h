@@ -64,8 +64,13 @@ typedef enum {
 
 /* Where the ideal (model) distribution's Gaussian parameters come from. */
 typedef enum {
-  QRNG_MODEL_FIT = 0,  /* mean and population s.d. of the same samples */
-  QRNG_MODEL_GIVEN = 1 /* the caller's mu, sigma (sigma > 0) */
+  QRNG_MODEL_FIT = 0,   /* mean and population s.d. of the same samples */
+  QRNG_MODEL_GIVEN = 1, /* the caller's mu, sigma (sigma > 0) */
+  /* Sec. II.B classical-noise subtraction: the samples' mean, and the
+   * quantum part of their s.d., sigma_q^2 = sigma_fit^2 - sigma_c^2 with the
+   * classical noise's s.d. sigma_c (measured with the source off) passed in
+   * `sigma` (>= 0); sigma_c >= sigma_fit leaves a point-mass model. */
+  QRNG_MODEL_QUANTUM = 2
 } qrng_model;
 
 typedef struct qrng_ctx qrng_ctx;
@@ -73,7 +78,7 @@ typedef struct qrng_ctx qrng_ctx;
 typedef struct {
   int32_t sample_bits; /* N, 1..8: ADC bits per sample */
   int32_t model;       /* qrng_model */
-  double mu, sigma;    /* used when model == QRNG_MODEL_GIVEN */
+  double mu, sigma;    /* QRNG_MODEL_GIVEN: both; QRNG_MODEL_QUANTUM: sigma = sigma_c */
   int32_t u_mode;      /* qrng_u_mode */
   int32_t reserved;    /* must be 0 */
 } qrng_me_opts;
@@ -125,6 +130,20 @@ void qrng_destroy(qrng_ctx *ctx);
 qrng_status qrng_minentropy(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
                             const qrng_me_opts *opts, qrng_me_result *out_host,
                             uint64_t *counts_host, void *stream);
+
+/* As qrng_minentropy on a random subset of the samples (Sec. II.C proposes
+ * estimating on randomly chosen raw data): sample t counts when the high 32
+ * bits of output t of SplitMix64 seeded with subset_seed -- mix(subset_seed +
+ * (t+1) 0x9e3779b97f4a7c15), mix = the generator's published finaliser
+ * (xor-shift 30, multiply 0xbf58476d1ce4e5b9, xor-shift 27, multiply
+ * 0x94d049bb133111eb, xor-shift 31) -- are below keep_thr, so about
+ * keep_thr / 2^32 of them count.  keep_thr == 0 counts every sample (the
+ * plain estimate).  counts_host (nullable) receives the subset's counts;
+ * out_host->samples is the number kept.  QRNG_EINVAL if none is kept. */
+qrng_status qrng_minentropy_subset(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
+                                   const qrng_me_opts *opts, uint64_t subset_seed,
+                                   uint32_t keep_thr, qrng_me_result *out_host,
+                                   uint64_t *counts_host, void *stream);
 
 /* Sec. III.B output length m = n H/N - 2 log2(1/eps), with H counted in whole
  * bits per sample (floor of h_mod, at least 0), the security term rounded up

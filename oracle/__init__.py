@@ -345,13 +345,16 @@ def minentropy_dists(P: np.ndarray, Pa: np.ndarray, N: int,
 
 def minentropy_counts(counts: np.ndarray, N: int, mu: float | None = None,
                       sigma: float | None = None,
-                      u_mode: int = U_MODEL_ARGMAX) -> dict:
+                      u_mode: int = U_MODEL_ARGMAX,
+                      sigma_classical: float | None = None) -> dict:
     """Min-entropy of an ADC histogram with the correction of Sec. II.C.
 
     P' = counts / S is the actual distribution.  The ideal P is the Gaussian
     ADC model; its mean and standard deviation are either given or measured
     from the same samples (population moments), as the paper measures the
-    noise variance (Sec. II.B).
+    noise variance (Sec. II.B).  With ``sigma_classical`` the model keeps only
+    the quantum part of the measured variance, sigma_q^2 = sigma_{q+c}^2 -
+    sigma_c^2 (Sec. II.B; a point mass when that is not positive).
     """
     c = np.asarray(counts, dtype=np.float64)
     S = float(c.sum())
@@ -359,7 +362,10 @@ def minentropy_counts(counts: np.ndarray, N: int, mu: float | None = None,
     v = np.arange(len(c), dtype=np.float64)
     if mu is None or sigma is None:
         mu_hat = float((v * c).sum() / S)
-        sigma_hat = math.sqrt(float((((v - mu_hat) ** 2) * c).sum() / S))
+        var = float((((v - mu_hat) ** 2) * c).sum() / S)
+        if sigma_classical is not None:
+            var -= float(sigma_classical) ** 2
+        sigma_hat = math.sqrt(var) if var > 0 else 0.0
     else:
         mu_hat, sigma_hat = float(mu), float(sigma)
     P = gaussian_model(N, mu_hat, sigma_hat)
@@ -367,6 +373,31 @@ def minentropy_counts(counts: np.ndarray, N: int, mu: float | None = None,
     out["mu_hat"] = mu_hat
     out["sigma_hat"] = sigma_hat
     return out
+
+
+SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    """Outputs 0..count-1 of the SplitMix64 generator (Steele, Lea and Flood,
+    OOPSLA 2014) from state `seed`: output t = mix(seed + (t+1) gamma), mix =
+    xor-shift 30, multiply 0xbf58476d1ce4e5b9, xor-shift 27, multiply
+    0x94d049bb133111eb, xor-shift 31 (all mod 2^64)."""
+    with np.errstate(over="ignore"):
+        t = np.arange(1, count + 1, dtype=np.uint64)
+        z = np.uint64(seed & (2 ** 64 - 1)) + t * np.uint64(SPLITMIX_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def subset_mask(S: int, seed: int, keep_thr: int) -> np.ndarray:
+    """The random subset of Sec. II.C's cheaper estimate: sample t is kept
+    when the high 32 bits of SplitMix64 output t are below keep_thr (all
+    samples when keep_thr is 0)."""
+    if keep_thr == 0:
+        return np.ones(S, dtype=bool)
+    return (splitmix64(seed, S) >> np.uint64(32)) < np.uint64(keep_thr)
 
 
 def histogram(samples: np.ndarray, N: int) -> np.ndarray:

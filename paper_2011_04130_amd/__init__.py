@@ -14,13 +14,13 @@ import ctypes
 import os
 
 from ._lib import (LIB_PATH, QrngError, PATH_AUTO, PATH_DIRECT, PATH_NTT, PATH_MFMA,
-                   U_MODEL_ARGMAX, U_BOTH_ARGMAX, U_ALL, MODEL_FIT, MODEL_GIVEN,
+                   U_MODEL_ARGMAX, U_BOTH_ARGMAX, U_ALL, MODEL_FIT, MODEL_GIVEN, MODEL_QUANTUM,
                    Block, MeOpts, MeResult, load_library, output_bits, version)
 from .api import Context
 
 __all__ = [
     "Context", "QrngError", "output_bits", "version", "load_library", "LIB_PATH",
     "PATH_AUTO", "PATH_DIRECT", "PATH_NTT", "PATH_MFMA",
-    "U_MODEL_ARGMAX", "U_BOTH_ARGMAX", "U_ALL", "MODEL_FIT", "MODEL_GIVEN",
+    "U_MODEL_ARGMAX", "U_BOTH_ARGMAX", "U_ALL", "MODEL_FIT", "MODEL_GIVEN", "MODEL_QUANTUM",
     "Block", "MeOpts", "MeResult",
 ]

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libqrng.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = 0, -1, -2, -3, -4, -5
 PATH_AUTO, PATH_DIRECT, PATH_NTT, PATH_MFMA = 0, 1, 2, 3
 U_MODEL_ARGMAX, U_BOTH_ARGMAX, U_ALL = 0, 1, 2
-MODEL_FIT, MODEL_GIVEN = 0, 1
+MODEL_FIT, MODEL_GIVEN, MODEL_QUANTUM = 0, 1, 2
 PLAN_ESTIMATE, PLAN_GRAPH, PLAN_TUNE = 1, 2, 4
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
@@ -86,7 +86,8 @@ _lib = None
 
 # every symbol the header declares
 EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
-           "qrng_minentropy", "qrng_output_bits", "qrng_toeplitz_hash",
+           "qrng_minentropy", "qrng_minentropy_subset", "qrng_output_bits",
+           "qrng_toeplitz_hash",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
            "qrng_modified_toeplitz_hash", "qrng_modified_toeplitz_hash_seeded",
            "qrng_toeplitz_hash_fft64",
@@ -121,6 +122,9 @@ def load_library(path: str | None = None):
     lib.qrng_minentropy.argtypes = [vp, vp, u64, ctypes.POINTER(MeOpts),
                                     ctypes.POINTER(MeResult), ctypes.POINTER(u64), vp]
     lib.qrng_minentropy.restype = i32
+    lib.qrng_minentropy_subset.argtypes = [vp, vp, u64, ctypes.POINTER(MeOpts), u64, u32,
+                                           ctypes.POINTER(MeResult), ctypes.POINTER(u64), vp]
+    lib.qrng_minentropy_subset.restype = i32
     lib.qrng_output_bits.argtypes = [u64, i32, ctypes.c_double, ctypes.c_double,
                                      ctypes.POINTER(u64)]
     lib.qrng_output_bits.restype = i32

@@ -9,8 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import (MODEL_FIT, MODEL_GIVEN, PATH_AUTO, PLAN_ESTIMATE, PLAN_GRAPH, PLAN_TUNE,
-                   U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, Served,
+from ._lib import (MODEL_FIT, MODEL_GIVEN, MODEL_QUANTUM, PATH_AUTO, PLAN_ESTIMATE, PLAN_GRAPH,
+                   PLAN_TUNE, U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, Served,
                    ServerCfg, ServerStats, check, kernel_names, load_library)
 
 
@@ -100,15 +100,18 @@ class Context:
     # -- Sec. II ------------------------------------------------------------
     def minentropy(self, samples, sample_bits: int = 8, model: int = MODEL_FIT,
                    mu: float = 0.0, sigma: float = 0.0, u_mode: int = U_MODEL_ARGMAX,
-                   stream=None, want_counts: bool = False) -> dict:
+                   stream=None, want_counts: bool = False, subset_seed: int = 0,
+                   keep_thr: int = 0) -> dict:
+        """Sec. II estimate of 1-byte samples (synchronous); keep_thr > 0
+        estimates on the random subset qrng_minentropy_subset keeps."""
         torch = self._torch
         p = self._dev_tensor(samples, "samples", torch.uint8)
         opts = MeOpts(sample_bits, model, mu, sigma, u_mode, 0)
         res = MeResult()
         counts = (ctypes.c_uint64 * (1 << sample_bits))() if want_counts else None
-        check(self._lib.qrng_minentropy(self._h, p, samples.numel(), ctypes.byref(opts),
-                                        ctypes.byref(res), counts,
-                                        _stream(torch, self.device, stream)))
+        check(self._lib.qrng_minentropy_subset(self._h, p, samples.numel(), ctypes.byref(opts),
+                                               subset_seed, keep_thr, ctypes.byref(res), counts,
+                                               _stream(torch, self.device, stream)))
         out = res.as_dict()
         if want_counts:
             out["counts"] = list(counts)

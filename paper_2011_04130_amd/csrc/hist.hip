@@ -31,6 +31,11 @@ __global__ __launch_bounds__(256) void k_hist_part(HistArgs a) {
   hist_part_body<256, HC>(a, blockIdx.x, h);
 }
 
+__global__ __launch_bounds__(256) void k_hist_part_subset(HistArgs a) {
+  __shared__ uint32_t h[HC * HB];
+  hist_part_body<256, HC, false, true>(a, blockIdx.x, h);
+}
+
 __global__ __launch_bounds__(256) void k_hist_finish(HistArgs a) {
   __shared__ FinishLds L;
   hist_finish_body<256>(a, L);
@@ -78,18 +83,23 @@ uint64_t hist_scratch_words() { return TICKET_WORD + 64; }
 
 hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
                          unsigned long long* counts_out, const MeDevArgs* finish,
-                         hipStream_t s) {
+                         hipStream_t s, uint64_t subset_seed, uint32_t keep_thr) {
   HistArgs a{};
   a.s = samples;
   a.S = S;
   a.N = N;
+  a.subset_seed = subset_seed;
+  a.keep_thr = keep_thr;
   a.part = scratch;
   a.G = hist_groups(S);
   a.counts = counts_out;
   a.finish = finish != nullptr;
   if (finish) a.me = *finish;
   prof_begin(KID_HIST, s);
-  hipLaunchKernelGGL(k_hist_part, dim3(a.G), dim3(256), 0, s, a);
+  if (keep_thr)
+    hipLaunchKernelGGL(k_hist_part_subset, dim3(a.G), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_hist_part, dim3(a.G), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_hist_finish, dim3(1), dim3(256), 0, s, a);
   prof_end(KID_HIST, s);
   return hipGetLastError();

@@ -138,7 +138,11 @@ __device__ void me_estimate(double cv, int N, int model, int u_mode, double mu_g
   } else {
     mu = s1 / S;
     const double d = (double)v - mu;
-    sigma = sqrt(block_sum<NW>(d * d * cv, red) / S);
+    // Sec. II.B: with the quantum model, the classical s.d. (sigma_given)
+    // is taken out of the variance
+    const double var = block_sum<NW>(d * d * cv, red) / S -
+                       (model == QRNG_MODEL_QUANTUM ? sigma_given * sigma_given : 0.0);
+    sigma = var > 0.0 ? sqrt(var) : 0.0;
   }
   // P(v) = Phi(v + 1/2) - Phi(v - 1/2), codes 0 and K-1 take the tails: each
   // boundary is evaluated once, by the thread below it
@@ -218,10 +222,24 @@ __device__ inline uint32_t merged(const uint32_t* h, int b) {
   return t;
 }
 
+// The estimate on a random subset of the samples (Sec. II.C suggests it as a
+// cheaper route): sample t is kept when the high 32 bits of output t of the
+// SplitMix64 generator seeded with `seed` (Steele, Lea and Flood's
+// counter-based form: mix(seed + (t+1) 0x9e3779b97f4a7c15)) are below thr.
+__device__ __forceinline__ bool subset_keep(uint64_t seed, uint64_t t, uint32_t thr) {
+  uint64_t z = seed + (t + 1) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (uint32_t)(z >> 32) < thr;
+}
+
 struct HistArgs {
   const uint8_t* s;
   uint64_t S;
   int N;
+  uint64_t subset_seed;  // with keep_thr > 0, only the kept samples count
+  uint32_t keep_thr;
   uint32_t* part;               // G rows of PS words: HB partial counts, zero pad
   uint32_t G;                   // workgroups that count
   unsigned long long* counts;   // nullable: the 2^N + 1 summed counts
@@ -238,12 +256,23 @@ __host__ __device__ inline unsigned hist_groups(uint64_t S) {
   return (unsigned)g;
 }
 
+// the 4 samples of word w, the first at sample index t, kept ones only
+__device__ inline void count_word_subset(uint32_t* hw, uint32_t w, uint32_t lim, uint64_t t,
+                                         uint64_t seed, uint32_t thr) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t x = (w >> (8 * b)) & 255u;
+    if (subset_keep(seed, t + b, thr)) atomicAdd(&hw[x < lim ? x : 256u], 1u);
+  }
+}
+
 // Workgroup wg (of a.G) counts its contiguous slice of the samples into
 // HCW LDS sub-histograms h (HCW * HB words) and stores their sum as partial
 // row wg (with COHERENT as device-scope atomic stores, which write through
-// to the level all dies share).  Bytes before the first 16-byte boundary and
-// after the last are counted one at a time by workgroup 0.
-template <int NT, int HCW, bool COHERENT = false>
+// to the level all dies share; with SUBSET only the kept samples).  Bytes
+// before the first 16-byte boundary and after the last are counted one at a
+// time by workgroup 0.
+template <int NT, int HCW, bool COHERENT = false, bool SUBSET = false>
 __device__ void hist_part_body(const HistArgs& a, uint32_t wg, uint32_t* h) {
   const int tid = threadIdx.x;
   for (int i = tid; i < HCW * HB; i += NT) h[i] = 0u;
@@ -260,34 +289,37 @@ __device__ void hist_part_body(const HistArgs& a, uint32_t wg, uint32_t* h) {
   const uint64_t v0 = (uint64_t)wg * per;
   const uint64_t v1 = v0 + per < nvec ? v0 + per : nvec;
   uint64_t i = v0 + tid;
+  // vector i holds samples head + 16 i .. head + 16 i + 15
+  auto count4 = [&](const uint4& v, uint64_t vi) {
+    if constexpr (SUBSET) {
+      const uint64_t t = head + 16 * vi;
+      count_word_subset(hw, v.x, lim, t, a.subset_seed, a.keep_thr);
+      count_word_subset(hw, v.y, lim, t + 4, a.subset_seed, a.keep_thr);
+      count_word_subset(hw, v.z, lim, t + 8, a.subset_seed, a.keep_thr);
+      count_word_subset(hw, v.w, lim, t + 12, a.subset_seed, a.keep_thr);
+    } else {
+      count_word(hw, v.x, lim);
+      count_word(hw, v.y, lim);
+      count_word(hw, v.z, lim);
+      count_word(hw, v.w, lim);
+    }
+  };
   for (; i + 3 * NT < v1; i += 4 * NT) {
     uint4 v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = s4[i + k * NT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      count_word(hw, v[k].x, lim);
-      count_word(hw, v[k].y, lim);
-      count_word(hw, v[k].z, lim);
-      count_word(hw, v[k].w, lim);
-    }
+    for (int k = 0; k < 4; ++k) count4(v[k], i + k * NT);
   }
-  for (; i < v1; i += NT) {
-    const uint4 v = s4[i];
-    count_word(hw, v.x, lim);
-    count_word(hw, v.y, lim);
-    count_word(hw, v.z, lim);
-    count_word(hw, v.w, lim);
-  }
+  for (; i < v1; i += NT) count4(s4[i], i);
+  auto count1 = [&](uint64_t j) {
+    const uint32_t x = a.s[j];
+    if (!SUBSET || subset_keep(a.subset_seed, j, a.keep_thr))
+      atomicAdd(&hw[x < lim ? x : 256u], 1u);
+  };
   if (wg == 0) {
-    for (uint64_t j = tid; j < head; j += NT) {
-      const uint32_t x = a.s[j];
-      atomicAdd(&hw[x < lim ? x : 256u], 1u);
-    }
-    for (uint64_t j = head + nvec * 16 + tid; j < a.S; j += NT) {
-      const uint32_t x = a.s[j];
-      atomicAdd(&hw[x < lim ? x : 256u], 1u);
-    }
+    for (uint64_t j = tid; j < head; j += NT) count1(j);
+    for (uint64_t j = head + nvec * 16 + tid; j < a.S; j += NT) count1(j);
   }
   __syncthreads();
   uint32_t* mine = a.part + (uint64_t)wg * PS;

@@ -168,10 +168,11 @@ uint64_t hist_scratch_words();
 // Two launches: histogram of S samples of N bits (N <= 8); counts_out
 // (nullable, device) receives the 2^N counts and then the number of samples
 // >= 2^N; with `finish` the estimate and m are written on the device.
-// S < 2^40.
+// S < 2^40.  keep_thr > 0: only the samples the seeded generator keeps count
+// (hist_dev.h, subset_keep).
 hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
                          unsigned long long* counts_out, const MeDevArgs* finish,
-                         hipStream_t s);
+                         hipStream_t s, uint64_t subset_seed = 0, uint32_t keep_thr = 0);
 
 // Per-block estimates of an uneven batch of 8-bit sample blocks (one
 // workgroup each): block b's histogram, estimate (out[b], nullable) and
@@ -206,5 +207,7 @@ bool ctx_pin_seed(qrng_ctx* c, uint32_t seed_id, int delta, uint64_t* L);
 void ctx_track_server(qrng_ctx* c, qrng_server* s, bool add);
 // Records the last error text (returns st).
 qrng_status set_error(qrng_status st, const char* fmt, ...);
+// Validates estimator options (model, U mode, reserved field, parameters).
+qrng_status check_me_opts(const qrng_me_opts& o);
 
 }  // namespace qrng

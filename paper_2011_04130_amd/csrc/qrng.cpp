@@ -352,7 +352,9 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
     mu = s1 / S;
     double s2 = 0.0;
     for (int v = 0; v < K; ++v) s2 += ((double)v - mu) * ((double)v - mu) * (double)c[v];
-    sigma = std::sqrt(s2 / S);
+    // Sec. II.B: the quantum part of the variance, sigma_q^2 = sigma^2 - sigma_c^2
+    const double var = s2 / S - (o.model == QRNG_MODEL_QUANTUM ? o.sigma * o.sigma : 0.0);
+    sigma = var > 0.0 ? std::sqrt(var) : 0.0;
   }
   std::vector<double> P(K);
   if (sigma > 0.0) {
@@ -429,6 +431,19 @@ qrng_status set_error(qrng_status st, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return st;
+}
+
+qrng_status check_me_opts(const qrng_me_opts& o) {
+  if (o.model != QRNG_MODEL_FIT && o.model != QRNG_MODEL_GIVEN && o.model != QRNG_MODEL_QUANTUM)
+    return fail(QRNG_EINVAL, "unknown model");
+  if (o.u_mode < QRNG_U_MODEL_ARGMAX || o.u_mode > QRNG_U_ALL)
+    return fail(QRNG_EINVAL, "unknown U mode");
+  if (o.reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
+  if (o.model == QRNG_MODEL_GIVEN && !(o.sigma > 0 && std::isfinite(o.sigma) && std::isfinite(o.mu)))
+    return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  if (o.model == QRNG_MODEL_QUANTUM && !(o.sigma >= 0 && std::isfinite(o.sigma)))
+    return fail(QRNG_EINVAL, "the quantum model needs a finite classical s.d. sigma >= 0");
+  return QRNG_OK;
 }
 
 void prof_begin(int kid, hipStream_t s) {
@@ -583,28 +598,32 @@ qrng_status qrng_output_bits(uint64_t n, int sample_bits, double h_mod, double l
 qrng_status qrng_minentropy(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
                             const qrng_me_opts* opts, qrng_me_result* out,
                             uint64_t* counts_host, void* stream) {
+  return qrng_minentropy_subset(ctx, samples, S, opts, 0, 0, out, counts_host, stream);
+}
+
+qrng_status qrng_minentropy_subset(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
+                                   const qrng_me_opts* opts, uint64_t subset_seed,
+                                   uint32_t keep_thr, qrng_me_result* out,
+                                   uint64_t* counts_host, void* stream) {
   if (!ctx || !samples || !opts || !out) return fail(QRNG_EINVAL, "null argument");
   const int N = opts->sample_bits;
   if (N < 1 || N > 8) return fail(QRNG_EINVAL, "sample_bits must be 1..8 for byte samples");
   if (S == 0) return fail(QRNG_EINVAL, "no samples");
   if (S >= (1ull << 40)) return fail(QRNG_EINVAL, "at most 2^40 - 1 samples per call");
-  if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
-    return fail(QRNG_EINVAL, "unknown model");
-  if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
-    return fail(QRNG_EINVAL, "unknown U mode");
-  if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
-  if (opts->model == QRNG_MODEL_GIVEN &&
-      !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
-    return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  if (qrng_status st_o = check_me_opts(*opts)) return st_o;
   DeviceGuard g(ctx->device);
   CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int K = 1 << N;
-  HIP_TRY(hist_estimate(samples, S, N, ctx->hist_scratch, ctx->counts_dev, nullptr, s));
+  HIP_TRY(hist_estimate(samples, S, N, ctx->hist_scratch, ctx->counts_dev, nullptr, s,
+                        subset_seed, keep_thr));
   HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 1) * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (ctx->counts_host[K])
     return fail(QRNG_EINVAL, "%llu samples are >= 2^%d", ctx->counts_host[K], N);
+  uint64_t kept = 0;
+  for (int v = 0; v < K; ++v) kept += ctx->counts_host[v];
+  if (kept == 0) return fail(QRNG_EINVAL, "the subset keeps no sample");
   if (counts_host)
     for (int v = 0; v < K; ++v) counts_host[v] = ctx->counts_host[v];
   minentropy_finish(ctx->counts_host, N, *opts, out);
@@ -719,14 +738,7 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
                          int path, void* stream) {
   if (!ctx || !samples || !opts || !y) return fail(QRNG_EINVAL, "null argument");
   if (opts->sample_bits != 8) return fail(QRNG_EINVAL, "qrng_extract hashes 8-bit samples");
-  if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
-    return fail(QRNG_EINVAL, "unknown model");
-  if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
-    return fail(QRNG_EINVAL, "unknown U mode");
-  if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
-  if (opts->model == QRNG_MODEL_GIVEN &&
-      !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
-    return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  if (qrng_status st_o = check_me_opts(*opts)) return st_o;
   if (std::isnan(log2_inv_eps) || log2_inv_eps < 0)
     return fail(QRNG_EINVAL, "bad security parameter");
   if (S == 0 || (S & 7)) return fail(QRNG_EINVAL, "S must be a positive multiple of 8");
@@ -1060,14 +1072,7 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
   if (estimate) {
     if (!opts || !m_dev) return fail(QRNG_EINVAL, "estimate plans need opts and m_dev");
     if (opts->sample_bits != 8) return fail(QRNG_EINVAL, "estimate plans take 8-bit samples");
-    if (opts->model != QRNG_MODEL_FIT && opts->model != QRNG_MODEL_GIVEN)
-      return fail(QRNG_EINVAL, "unknown model");
-    if (opts->u_mode < QRNG_U_MODEL_ARGMAX || opts->u_mode > QRNG_U_ALL)
-      return fail(QRNG_EINVAL, "unknown U mode");
-    if (opts->reserved != 0) return fail(QRNG_EINVAL, "reserved field must be 0");
-    if (opts->model == QRNG_MODEL_GIVEN &&
-        !(opts->sigma > 0 && std::isfinite(opts->sigma) && std::isfinite(opts->mu)))
-      return fail(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+    if (qrng_status st_o = check_me_opts(*opts)) return st_o;
     if (std::isnan(log2_inv_eps) || log2_inv_eps < 0)
       return fail(QRNG_EINVAL, "bad security parameter");
   }

@@ -261,14 +261,7 @@ qrng_status qrng_server_create(qrng_ctx* ctx, const qrng_server_cfg* cfg, qrng_s
   if (!ctx || !cfg) return err(QRNG_EINVAL, "null argument");
   const qrng_server_cfg& c = *cfg;
   if (c.opts.sample_bits != 8) return err(QRNG_EINVAL, "serving takes 8-bit samples");
-  if (c.opts.model != QRNG_MODEL_FIT && c.opts.model != QRNG_MODEL_GIVEN)
-    return err(QRNG_EINVAL, "unknown model");
-  if (c.opts.u_mode < QRNG_U_MODEL_ARGMAX || c.opts.u_mode > QRNG_U_ALL)
-    return err(QRNG_EINVAL, "unknown U mode");
-  if (c.opts.reserved) return err(QRNG_EINVAL, "reserved field must be 0");
-  if (c.opts.model == QRNG_MODEL_GIVEN &&
-      !(c.opts.sigma > 0 && std::isfinite(c.opts.sigma) && std::isfinite(c.opts.mu)))
-    return err(QRNG_EINVAL, "given model needs finite mu and sigma > 0");
+  if (qrng_status st_o = check_me_opts(c.opts)) return st_o;
   if (std::isnan(c.log2_inv_eps) || c.log2_inv_eps < 0)
     return err(QRNG_EINVAL, "bad security parameter");
   if (c.block_bits % 512) return err(QRNG_EINVAL, "block_bits must be a multiple of 512");

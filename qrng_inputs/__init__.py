@@ -14,6 +14,11 @@ Recipe (the paper's raw data files are not available; these stand in):
 * Toeplitz seeds: ``default_rng(seed).integers(0, 2**64, ceil(L/64))`` words.
   Bits at positions >= L are left random on purpose: consumers must ignore
   them.
+* Adversarial ADC stream (the attacked detector of Sec. II.B): intensity
+  I ~ N(0, 1), photodiode gain alpha(I) = alpha_e (1 - I / (beta_e I_max))
+  with alpha_e = 0.99, beta_e = 2, I_max = 5, output V' = alpha(I) I,
+  digitised by an N-bit ADC over [-5, 5): code floor((V' + 5) / (10 / 2^N)),
+  clipped to [0, 2^N - 1] (the end codes take the tails).
 * Named workloads: ``config(k)`` returns the fixed seeds and sizes of the
   five workloads (single block n = 2^17; single block n = 2^23; block-length
   sweep over a 2^30-bit stream; 4096 uneven batched blocks; serving loop).
@@ -43,6 +48,17 @@ def gen_adc(S: int, sigma: float = 20.0, mu: float = 128.0, seed: int = 0,
     z = rng.standard_normal(S)
     u = np.clip(np.rint(mu + sigma * z), 0, (1 << bits) - 1)
     return u.astype(np.uint8)
+
+
+def gen_attack(S: int, bits: int = 5, seed: int = 0, alpha_e: float = 0.99,
+               beta_e: float = 2.0, i_max: float = 5.0) -> np.ndarray:
+    """S samples of the attacked detector output V' = alpha(I) I as N-bit
+    ADC codes over [-5, 5) (uint8)."""
+    rng = np.random.default_rng(seed)
+    i = rng.standard_normal(S)
+    v = alpha_e * (1.0 - i / (beta_e * i_max)) * i
+    w = 10.0 / (1 << bits)
+    return np.clip(np.floor((v + 5.0) / w), 0, (1 << bits) - 1).astype(np.uint8)
 
 
 def gen_seed_words(L: int, seed: int = 0) -> np.ndarray:

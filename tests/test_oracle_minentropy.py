@@ -169,3 +169,41 @@ def test_tie_between_model_bins_takes_lowest_value():
         r = oracle.minentropy_dists(P, P, 8)
         assert r["argmax_model"] == k
         assert r["h_min"] == -math.log2(P.max())
+
+
+def test_splitmix64_published_output_and_subset():
+    # the generator's first output from state 0 is the published 0xe220a8397b1dcdaf
+    assert int(oracle.splitmix64(0, 1)[0]) == 0xE220A8397B1DCDAF
+    # keep_thr 0 keeps everything; the kept fraction follows keep_thr / 2^32
+    assert oracle.subset_mask(1000, 9, 0).all()
+    S = 1 << 18
+    for thr in (1 << 28, 1 << 30, 3 << 30):
+        frac = float(oracle.subset_mask(S, 77, thr).mean())
+        p = thr / 2.0 ** 32
+        assert abs(frac - p) < 5 * np.sqrt(p * (1 - p) / S)
+    # subsets of growing threshold are nested (same generator outputs)
+    a = oracle.subset_mask(S, 5, 1 << 29)
+    b = oracle.subset_mask(S, 5, 1 << 30)
+    assert not (a & ~b).any()
+
+
+def test_classical_noise_subtraction():
+    # Sec. II.B: sigma_q^2 = sigma_{q+c}^2 - sigma_c^2.  sigma_c = 0 is the fit;
+    # the model then equals the given-parameter route at (mu_fit, sigma_q); a
+    # larger classical part narrows the model and lowers H_min; sigma_c at or
+    # above the fitted s.d. leaves a point mass (H_min = 0)
+    s = np.clip(np.rint(128 + 20 * np.random.default_rng(8).standard_normal(1 << 16)),
+                0, 255).astype(np.uint8)
+    h = oracle.histogram(s, 8)
+    fit = oracle.minentropy_counts(h, 8)
+    assert oracle.minentropy_counts(h, 8, sigma_classical=0.0)["h_min"] == fit["h_min"]
+    prev = fit["h_min"]
+    for sc in (5.0, 10.0, 15.0):
+        r = oracle.minentropy_counts(h, 8, sigma_classical=sc)
+        sq = math.sqrt(fit["sigma_hat"] ** 2 - sc * sc)
+        assert abs(r["sigma_hat"] - sq) < 1e-12
+        g = oracle.minentropy_counts(h, 8, mu=fit["mu_hat"], sigma=sq)
+        assert abs(r["h_min"] - g["h_min"]) < 1e-12
+        assert r["h_min"] < prev
+        prev = r["h_min"]
+    assert oracle.minentropy_counts(h, 8, sigma_classical=fit["sigma_hat"] + 1)["h_min"] == 0.0
