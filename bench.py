@@ -344,6 +344,45 @@ def bench_fft64(ctx, q, torch, qi, reps=10):
                                "note": "streamed bytes of all its passes over the whole call"}}
 
 
+def bench_estimator(ctx, q, torch, qi, reps=10):
+    """Sec. II.B-II.C estimator workloads on the device: the estimate of a
+    2^24-sample window (the serving window) in full and on random subsets
+    (1/8 and 1/64 of the samples), device time of the histogram and finish
+    only; and the attacked-detector source (2^20 samples, 5- and 8-bit ADC):
+    H_modify under each U reading against the observed -log2 max P'."""
+    import numpy as np
+    S = 1 << 24
+    s = torch.from_numpy(qi.gen_adc(S, 20.0, seed=71)).to("cuda:0")
+    res = {"window_samples": S, "rates": {}}
+    for name, thr in (("all", 0), ("1/8", 1 << 29), ("1/64", 1 << 26)):
+        ctx.minentropy(s, subset_seed=5, keep_thr=thr)  # first launch loads the kernels
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(reps):
+            me = ctx.minentropy(s, subset_seed=5, keep_thr=thr)
+        pr = ctx.profile_read()
+        ctx.profile(False)
+        c, ms = pr["histogram"]
+        us = ms / c * 1e3
+        res["rates"][name] = {"us": round(us, 1), "samples_per_s": round(S / us * 1e6 / 1e9, 2),
+                              "unit": "G samples/s", "kept": int(me["samples"]),
+                              "h_mod": round(me["h_mod"], 4)}
+    att = {}
+    for bits in (5, 8):
+        a = qi.gen_attack(1 << 20, bits, seed=60 + bits)
+        at = torch.from_numpy(a).to("cuda:0")
+        row = {}
+        for uname, u in (("argmax_P", q.U_MODEL_ARGMAX), ("both_argmax", q.U_BOTH_ARGMAX),
+                         ("all", q.U_ALL)):
+            me = ctx.minentropy(at, sample_bits=bits, u_mode=u, want_counts=True)
+            row[uname] = round(me["h_mod"], 4)
+        c = np.array(me["counts"], dtype=np.float64)
+        row["observed_h_min"] = round(float(-np.log2(c.max() / c.sum())), 4)
+        att["%d_bit" % bits] = row
+    res["attacked_detector"] = att
+    return res
+
+
 def bench_sweep(ctx, q, torch, qi, reps=3):
     """A 2^30-bit raw sequence (2^27 ADC samples) cut into blocks of n = 2^12
     .. 2^24 bits, every block hashed with one seed at m = 5n/8; raw Gbit/s per
@@ -483,7 +522,10 @@ def main():
                     help="also time the modified Toeplitz hash against the ordinary one")
     ap.add_argument("--fft64", type=int, default=1,
                     help="also time the paper's float64 method against the NTT path")
-    ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified", "fft64"],
+    ap.add_argument("--estimator", type=int, default=1,
+                    help="also time the subset estimate and run the attacked-detector source")
+    ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified", "fft64",
+                                       "estimator"],
                     help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
@@ -512,7 +554,8 @@ def main():
     if args.only:
         ctx = q.Context(0)
         fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve,
-              "modified": bench_modified, "fft64": bench_fft64}[args.only]
+              "modified": bench_modified, "fft64": bench_fft64,
+              "estimator": bench_estimator}[args.only]
         print(json.dumps(fn(ctx, q, torch, qi)))
         ctx.close()
         return
@@ -650,6 +693,8 @@ def main():
         out["modified_toeplitz"] = bench_modified(ctx, q, torch, qi)
     if args.fft64:
         out["paper_method_fft64"] = bench_fft64(ctx, q, torch, qi)
+    if args.estimator:
+        out["estimator"] = bench_estimator(ctx, q, torch, qi)
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:

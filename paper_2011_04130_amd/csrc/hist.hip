@@ -26,14 +26,17 @@ using namespace hd;
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_hist_part(HistArgs a) {
+// threads of a counting workgroup
+constexpr int PART_T = 1024;
+
+__global__ __launch_bounds__(PART_T) void k_hist_part(HistArgs a) {
   __shared__ uint32_t h[HC * HB];
-  hist_part_body<256, HC>(a, blockIdx.x, h);
+  hist_part_body<PART_T, HC>(a, blockIdx.x, h);
 }
 
-__global__ __launch_bounds__(256) void k_hist_part_subset(HistArgs a) {
+__global__ __launch_bounds__(PART_T) void k_hist_part_subset(HistArgs a) {
   __shared__ uint32_t h[HC * HB];
-  hist_part_body<256, HC, false, true>(a, blockIdx.x, h);
+  hist_part_body<PART_T, HC, false, true>(a, blockIdx.x, h);
 }
 
 __global__ __launch_bounds__(256) void k_hist_finish(HistArgs a) {
@@ -97,9 +100,9 @@ hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* sc
   if (finish) a.me = *finish;
   prof_begin(KID_HIST, s);
   if (keep_thr)
-    hipLaunchKernelGGL(k_hist_part_subset, dim3(a.G), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_hist_part_subset, dim3(a.G), dim3(PART_T), 0, s, a);
   else
-    hipLaunchKernelGGL(k_hist_part, dim3(a.G), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_hist_part, dim3(a.G), dim3(PART_T), 0, s, a);
   hipLaunchKernelGGL(k_hist_finish, dim3(1), dim3(256), 0, s, a);
   prof_end(KID_HIST, s);
   return hipGetLastError();
