@@ -289,14 +289,15 @@ def test_extract_matches_oracle(torch, ctx, cfg_k, path, cap_frac):
         ctx.unregister_seed(sid)
 
 
-@pytest.mark.parametrize("logn", [21, 22, 23])
-def test_extract_estimate_in_column_pass(torch, ctx, logn):
+@pytest.mark.parametrize("S", [1 << 18, 1 << 19, 1 << 20, 300008])
+def test_extract_estimate_in_column_pass(torch, ctx, S):
     """On the split transform (columns of 2^7, 2^8, 2^9) the estimate runs in
     extra workgroups of the first column pass, handing over through a ticket
     that each call leaves at zero: consecutive calls with different sources,
-    a direct-path call in between, each against the oracle."""
-    n = 1 << logn
-    S = n // 8
+    a direct-path call in between, each against the oracle (S = 300008: a
+    sample count that splits unevenly over the counting workgroups)."""
+    n = 8 * S
+    logn = n.bit_length() - 1
     sw = qi.gen_seed_words(2 * n - 1, 900 + logn)
     sid = ctx.register_seed(dev(torch, sw), 2 * n - 1)
     try:
