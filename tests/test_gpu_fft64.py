@@ -49,7 +49,9 @@ def ref_hash(xw, n, sw, m):
 
 SIZES = [(1, 1), (2, 1), (5, 3), (31, 17), (64, 64), (65, 1), (100, 100), (1000, 625),
          (4095, 4000), (4096, 2560), (10007, 5003), (65536, 40960), (200003, 100001),
-         (1 << 20, 655360)]
+         (1 << 20, 655360),
+         # n+m-1 just above 2^24: a 2^25-point transform (radix 2 first, six of 16)
+         (8388609, 8388609)]
 
 
 @pytest.mark.parametrize("n,m", SIZES)

@@ -52,7 +52,9 @@ def ref_modified(xw, n, aw, m):
 
 SIZES = [(1, 1), (2, 1), (2, 2), (64, 64), (65, 1), (100, 60), (130, 97), (1000, 625),
          (4096, 2560), (10007, 5003), (65536, 40960), (100000, 99999), (200003, 150001),
-         (1 << 20, 655360), (3000001, 2000001)]
+         (1 << 20, 655360), (3000001, 2000001),
+         # split transform with two raw and three output chunks (n-m < 2^23 < n-1)
+         (1 << 24, 10485760)]
 
 
 @pytest.mark.parametrize("n,m", SIZES)
