@@ -261,9 +261,17 @@ struct ColFwdArgs {
   hd::HistArgs est;
 };
 
-constexpr int COLS = 32;    // columns per workgroup (128-byte rows)
-constexpr int CSLOTS = 16;  // 512 threads = 32 columns x 16 slots
-constexpr int CGMAX = 2;    // groups in flight per thread
+constexpr int COLS = 32;  // columns per workgroup (128-byte rows)
+constexpr int CGMAX = 2;  // groups in flight per thread
+// slots (threads per column) of a column workgroup, 32 columns each: 16
+// (512 threads), and 32 for the inverse 2^9-point columns, where the extra
+// waves hide more of the input loads and barriers (one group per thread in
+// the radix-16 rounds).  The forward pass keeps 512: its estimate workgroups
+// need more registers, and at 1024 threads only one workgroup would fit a CU.
+template <int LOG1, bool INV>
+constexpr int cslots() {
+  return INV && LOG1 >= 9 ? 32 : 16;
+}
 
 // sub-histogram copies of an estimate workgroup in the column LDS
 template <int LOG1>
@@ -272,7 +280,9 @@ constexpr int est_copies() {
 }
 
 template <int LOG1>
-__global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTables tw) {
+__global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(ColFwdArgs a,
+                                                                            TwTables tw) {
+  constexpr int NS = cslots<LOG1, false>();
   __shared__ __align__(16) uint32_t lds[(1 << LOG1) * COLS];
   __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
   if (blockIdx.x < a.hg) {
@@ -281,7 +291,7 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
                         sizeof(hd::FinishLds) <= sizeof(lds),
                     "estimate workgroup fits the column LDS");
       if (blockIdx.y == 0)
-        hd::estimate_workgroup<COLS * CSLOTS, est_copies<LOG1>()>(a.est, blockIdx.x, a.ticket,
+        hd::estimate_workgroup<COLS * NS, est_copies<LOG1>()>(a.est, blockIdx.x, a.ticket,
                                                                   lds);
     }
     return;
@@ -304,7 +314,7 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   const int l2 = a.log2;
 
-  for (int j1 = threadIdx.x; j1 < (1 << LOG1); j1 += COLS * CSLOTS)
+  for (int j1 = threadIdx.x; j1 < (1 << LOG1); j1 += COLS * NS)
     wbits[j1] = stage_word(bits, mp, (j1 << l2) + bx * COLS, Nc);
   __syncthreads();
   auto ld_bits = [&](int g, int e) -> uint32_t {
@@ -341,13 +351,13 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_fwd(ColFwdArgs a, TwTable
   static_for<0, K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if constexpr (K == 1)
-      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_bits, st_out);
+      round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_bits, st_out);
     else if constexpr (k == 0)
-      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_bits, st_lds_k(kc));
+      round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_bits, st_lds_k(kc));
     else if constexpr (k == K - 1)
-      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_out);
+      round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_out);
     else
-      round_all<LOG1, k, CSLOTS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
+      round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k < K - 1) __syncthreads();
   });
 }
@@ -373,7 +383,9 @@ __device__ __forceinline__ uint64_t valid_bits(uint64_t m, const uint64_t* m_dev
 }
 
 template <int LOG1>
-__global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTables tw) {
+__global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColInvArgs a,
+                                                                           TwTables tw) {
+  constexpr int NS = cslots<LOG1, true>();
   __shared__ uint32_t lds[(1 << LOG1) * COLS];
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int lane = threadIdx.x & 63;
@@ -440,13 +452,13 @@ __global__ __launch_bounds__(COLS* CSLOTS) void k_cols_inv(ColInvArgs a, TwTable
   static_for_down<0, K>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if constexpr (K == 1)
-      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_in, st_bits);
+      round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_in, st_bits);
     else if constexpr (k == K - 1)
-      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_in, st_lds_k(kc));
+      round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_in, st_lds_k(kc));
     else if constexpr (k == 0)
-      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_bits);
+      round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_bits);
     else
-      round_all<LOG1, k, CSLOTS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_lds_k(kc));
+      round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k > 0) __syncthreads();
   });
 }
@@ -791,14 +803,14 @@ __global__ __launch_bounds__(256) void k_combine3(uint32_t* __restrict__ W, uint
 template <int LOG1>
 hipError_t launch_cols_fwd(const ColFwdArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
   prof_begin(KID_COLS_FWD, s);
-  hipLaunchKernelGGL(k_cols_fwd<LOG1>, grid, dim3(COLS * CSLOTS), 0, s, a, tw);
+  hipLaunchKernelGGL(k_cols_fwd<LOG1>, grid, dim3(COLS * cslots<LOG1, false>()), 0, s, a, tw);
   prof_end(KID_COLS_FWD, s);
   return hipGetLastError();
 }
 template <int LOG1>
 hipError_t launch_cols_inv(const ColInvArgs& a, dim3 grid, const TwTables& tw, hipStream_t s) {
   prof_begin(KID_COLS_INV, s);
-  hipLaunchKernelGGL(k_cols_inv<LOG1>, grid, dim3(COLS * CSLOTS), 0, s, a, tw);
+  hipLaunchKernelGGL(k_cols_inv<LOG1>, grid, dim3(COLS * cslots<LOG1, true>()), 0, s, a, tw);
   prof_end(KID_COLS_INV, s);
   return hipGetLastError();
 }
