@@ -7,11 +7,11 @@
 // samples into LDS sub-histograms and stores their sum as its partial
 // histogram; one workgroup of the second adds the partials up and computes
 // the estimate (thread v owns value v).  (A single launch whose last
-// workgroup finishes needs a device-scope fence in every workgroup, which
-// costs an L2 write-back per workgroup on this multi-die part; on its own
-// the launch boundary is cheaper.  The transform path hides that cost by
-// running the counting workgroups inside its first pass instead, see
-// estimate_workgroup.)  Values >= 2^N are counted apart so the host can
+// workgroup finishes, as estimate_workgroup does inside the transform's
+// first pass, measured slower on its own than the launch boundary: with a
+// device-scope fence per workgroup, an L2 write-back each on this multi-die
+// part; with the rows stored write-through, the 1024-thread finish at the
+// end of the counting.)  Values >= 2^N are counted apart so the host can
 // reject them.
 #include <math.h>
 
