@@ -56,6 +56,8 @@ ME_CASES = [
     ("ragged", 100003, 20.0, 128.0, 5, 8),
     ("five_bit", 50000, 5.0, 16.0, 6, 5),
     ("clipped_low", 30001, 30.0, 10.0, 7, 8),
+    # the most counting workgroups a launch uses (256 partial rows), ragged tail
+    ("window_2^22", (1 << 22) + 5, 20.0, 128.0, 8, 8),
 ]
 
 
@@ -108,6 +110,14 @@ def test_minentropy_errors_and_degenerate(torch, ctx):
         ctx.minentropy(torch.from_numpy(s).to("cuda:0"), sample_bits=5)
     with pytest.raises(q.QrngError):
         ctx.minentropy(torch.from_numpy(s).to("cuda:0"), model=1, sigma=0.0)
+    # one out-of-range value in the last partial row of the largest launch
+    big = qi.gen_adc((1 << 22) + 5, 5.0, 16.0, seed=10, bits=5)
+    big[-3] = 33
+    with pytest.raises(q.QrngError):
+        ctx.minentropy(torch.from_numpy(big).to("cuda:0"), sample_bits=5)
+    big[-3] = 31
+    got = ctx.minentropy(torch.from_numpy(big).to("cuda:0"), sample_bits=5, want_counts=True)
+    assert np.array_equal(np.array(got["counts"], dtype=np.uint64), oracle.histogram(big, 5))
     const = np.full(1000, 77, dtype=np.uint8)
     got = ctx.minentropy(torch.from_numpy(const).to("cuda:0"))
     want = oracle.minentropy_counts(oracle.histogram(const, 8), 8)
