@@ -303,20 +303,36 @@ def bench_modified(ctx, q, torch, qi, reps=30):
     return res
 
 
+def fft64_passes(lg):
+    """Stockham passes of a length-2^lg transform as the library plans them:
+    radix 2/4/8 when lg is not a multiple of 4, radix 16, radix 256 while
+    8 or more levels remain, radix 16 for the rest."""
+    passes = 1 if lg % 4 else 0
+    rem = lg - lg % 4
+    if rem >= 4:
+        passes += 1
+        rem -= 4
+    passes += rem // 8 + (1 if rem % 8 else 0)
+    return passes
+
+
 def fft64_stream_bytes(n, m):
-    """HBM bytes the float64 method streams per hash: the pack pass writes N
-    complex doubles; each Stockham pass reads and writes N (radix 16, plus a
-    radix 2/4/8 pass when log2 N is not a multiple of 4), for the forward and
-    the inverse transform; the product reads and writes N; the rounding pass
-    reads m and writes m/8."""
+    """HBM bytes the float64 method streams per hash: each Stockham pass
+    reads and writes N complex doubles, for the forward and the inverse
+    transform; the first forward pass reads the seed and raw bits itself when
+    it is the staged radix-16 pass (log2 N a multiple of 4, N >= 4096), else a
+    pack pass writes N first; the product reads and writes N; the rounding
+    pass reads m and writes m/8."""
     L = n + m - 1
     N = 16
     while N < L:
         N <<= 1
     lg = N.bit_length() - 1
-    passes = lg // 4 + (1 if lg % 4 else 0)
+    passes = fft64_passes(lg)
     c = 16
-    return N, 16 * N + 2 * passes * 2 * c * N + 2 * c * N + c * m + m // 8
+    fused = lg % 4 == 0 and N >= 4096
+    first_in = (n + L) // 8 - c * N if fused else c * N
+    return N, first_in + 2 * passes * 2 * c * N + 2 * c * N + c * m + m // 8
 
 
 def bench_fft64(ctx, q, torch, qi, reps=10):

@@ -10,10 +10,13 @@
 //
 // Both real inputs share one complex transform (z = a + i r; the two spectra
 // are separated from Z[k] and conj Z[N-k]), so a hash costs one forward and
-// one inverse complex transform of length N plus two elementwise passes.
-// Transforms are Stockham autosort passes (no bit reversal), radix 16 with
-// a radix 2/4/8 pass first when log2 N is not a multiple of 4, one 16-point
-// DFT in registers per thread, twiddles from sincospi.
+// one inverse complex transform of length N plus two elementwise passes (and
+// a packing pass, unless the first forward pass reads the bits itself).
+// Transforms are Stockham autosort passes (no bit reversal): a radix 2/4/8
+// pass first when log2 N is not a multiple of 4, a radix-16 pass, then
+// radix-256 passes (two 16-point DFT steps through LDS per sweep of the
+// array) while at least 8 levels remain, and a last radix-16 pass for the
+// rest; 16-point DFTs in registers, twiddles from sincospi.
 #include <math.h>
 
 #include "common.h"
@@ -93,17 +96,27 @@ __device__ __forceinline__ void dft_small(cplx (&v)[R]) {
   for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
-// z[q] = (seed bit q, raw bit q) for q < N (0 past L and n); clears *err.
-__global__ __launch_bounds__(256) void k_fft_pack(const uint32_t* __restrict__ seed, uint64_t L,
-                                                  const uint32_t* __restrict__ x, uint64_t n,
-                                                  cplx* __restrict__ z, uint64_t N,
-                                                  unsigned long long* err) {
+
+// Input q of the forward transform, (seed bit q, raw bit q), 0 past L and n.
+struct PackedIn {
+  const uint32_t* seed;
+  uint64_t L;
+  const uint32_t* x;
+  uint64_t n;
+  unsigned long long* err;  // cleared by the first thread (nullable)
+};
+__device__ __forceinline__ cplx packed_at(const PackedIn& p, uint64_t q) {
+  const double a = q < p.L ? (double)((p.seed[q >> 5] >> (q & 31)) & 1u) : 0.0;
+  const double r = q < p.n ? (double)((p.x[q >> 5] >> (q & 31)) & 1u) : 0.0;
+  return {a, r};
+}
+
+// z[q] = (seed bit q, raw bit q) for q < N; clears *err.
+__global__ __launch_bounds__(256) void k_fft_pack(PackedIn pk, cplx* __restrict__ z, uint64_t N) {
   const uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q == 0 && err) *err = 0ull;
+  if (q == 0 && pk.err) *pk.err = 0ull;
   if (q >= N) return;
-  const double a = q < L ? (double)((seed[q >> 5] >> (q & 31)) & 1u) : 0.0;
-  const double r = q < n ? (double)((x[q >> 5] >> (q & 31)) & 1u) : 0.0;
-  z[q] = {a, r};
+  z[q] = packed_at(pk, q);
 }
 
 // One Stockham pass of radix R over N points: sub-transforms of length Ns
@@ -134,6 +147,96 @@ __global__ __launch_bounds__(256) void k_fft_pass(const cplx* __restrict__ in,
   const uint64_t o = (j / Ns) * Ns * R + k;
 #pragma unroll
   for (int r = 0; r < R; ++r) out[o + r * Ns] = v[r];
+}
+
+// The first pass when it has radix 16 (Ns = 1: no twiddles, outputs j 16 +
+// r): the 256 j of a workgroup own 4096 consecutive outputs, staged through
+// LDS so that the stores are coalesced (N >= 4096).  BITS: the forward
+// transform's first pass reads the seed and raw bits itself (no pack pass).
+template <bool INV, bool BITS>
+__global__ __launch_bounds__(256) void k_fft_first16(const cplx* __restrict__ in,
+                                                     cplx* __restrict__ out, uint64_t N,
+                                                     PackedIn pk) {
+  __shared__ cplx st[256 * 17];  // [j][r], rows padded to 17
+  const int t = threadIdx.x;
+  const uint64_t stride = N >> 4;
+  const uint64_t j = (uint64_t)blockIdx.x * 256 + t;
+  cplx v[16];
+  if constexpr (BITS) {
+    if (j == 0 && pk.err) *pk.err = 0ull;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = packed_at(pk, j + r * stride);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = in[j + r * stride];
+  }
+  dft_small<16, INV>(v);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) st[t * 17 + r] = v[r];
+  __syncthreads();
+  cplx* __restrict__ o = out + (uint64_t)blockIdx.x * 4096;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
+    o[e] = st[(e >> 4) * 17 + (e & 15)];
+  }
+}
+
+// The same pass with radix 256 = 16 x 16, both steps in LDS (Ns >= 16, N >=
+// 4096): a workgroup takes 16 consecutive j (consecutive k, since 16 | Ns)
+// and all 256 inputs of each.  With x[r] the twiddled inputs and r = r1 +
+// 16 r2, r' = a + 16 b:  X[r'] = sum_r1 w16^(r1 b) w256^(r1 a) sum_r2
+// x[r1 + 16 r2] w16^(r2 a), so thread (jj, q) first does the inner DFT for
+// r1 = q, then the outer one for a = q.
+template <bool INV>
+__global__ __launch_bounds__(256) void k_fft_pass256(const cplx* __restrict__ in,
+                                                     cplx* __restrict__ out, uint64_t N,
+                                                     uint64_t Ns) {
+  __shared__ cplx buf[256 * 17];  // [r][jj], rows padded to 17
+  __shared__ cplx w256[256];      // exp(sign 2 pi i e / 256)
+  const int t = threadIdx.x;
+  const int jj = t & 15, q = t >> 4;
+  const uint64_t stride = N >> 8;
+  const uint64_t j0 = (uint64_t)blockIdx.x * 16;
+  {
+    double s, c;
+    sincospi((double)t / 128.0, &s, &c);
+    w256[t] = {c, INV ? s : -s};
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = q + 16 * i;
+    buf[r * 17 + jj] = in[j0 + jj + (uint64_t)r * stride];
+  }
+  __syncthreads();
+  const uint64_t j = j0 + jj;
+  const uint64_t k = j % Ns;
+  cplx v[16];
+  // inner DFT over r2 for r1 = q, after the pass twiddle exp(sign 2 pi i r k / (Ns 256))
+  const double base = (INV ? 2.0 : -2.0) * (double)k / (double)(Ns * 256);
+#pragma unroll
+  for (int r2 = 0; r2 < 16; ++r2) {
+    const int r = q + 16 * r2;
+    v[r2] = buf[r * 17 + jj];
+    if (r) {
+      double s, c;
+      sincospi(base * r, &s, &c);
+      v[r2] = cmul(v[r2], cplx{c, s});
+    }
+  }
+  dft_small<16, INV>(v);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a)
+    buf[(a * 16 + q) * 17 + jj] = a ? cmul(v[a], w256[(q * a) & 255]) : v[a];
+  __syncthreads();
+  // outer DFT over r1 for a = q
+#pragma unroll
+  for (int r1 = 0; r1 < 16; ++r1) v[r1] = buf[(q * 16 + r1) * 17 + jj];
+  dft_small<16, INV>(v);
+  const uint64_t o = (j / Ns) * Ns * 256 + k;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) out[o + (uint64_t)(q + 16 * b) * Ns] = v[b];
 }
 
 // Separate the two real inputs' spectra from Z = F(a + i r) and multiply:
@@ -189,10 +292,17 @@ __global__ __launch_bounds__(256) void k_fft_bits(const cplx* __restrict__ K, ui
   }
 }
 
+// Transform of length N from a (pk non-null: from the packed bits, a being
+// only scratch) ping-ponging with b; *result is the buffer holding the output.
 template <bool INV>
-hipError_t transform(cplx* a, cplx* b, uint64_t N, hipStream_t s, cplx** result) {
+hipError_t transform(cplx* a, cplx* b, uint64_t N, const PackedIn* pk, hipStream_t s,
+                     cplx** result) {
   int log = 0;
   while ((1ull << log) < N) ++log;
+  // the first pass reads the bits itself when it is the staged radix-16 one
+  const bool fuse = pk && log % 4 == 0 && N >= 4096;
+  if (pk && !fuse)
+    hipLaunchKernelGGL(k_fft_pack, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, *pk, a, N);
   cplx* in = a;
   cplx* out = b;
   uint64_t Ns = 1;
@@ -203,15 +313,35 @@ hipError_t transform(cplx* a, cplx* b, uint64_t N, hipStream_t s, cplx** result)
       case 2: hipLaunchKernelGGL((k_fft_pass<2, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
       case 4: hipLaunchKernelGGL((k_fft_pass<4, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
       case 8: hipLaunchKernelGGL((k_fft_pass<8, INV>), grid, dim3(256), 0, s, in, out, N, Ns); break;
-      default: hipLaunchKernelGGL((k_fft_pass<16, INV>), grid, dim3(256), 0, s, in, out, N, Ns);
+      case 16:
+        if (Ns == 1 && N >= 4096 && fuse)
+          hipLaunchKernelGGL((k_fft_first16<INV, true>), dim3((unsigned)(N / 4096)), dim3(256), 0,
+                             s, in, out, N, *pk);
+        else if (Ns == 1 && N >= 4096)
+          hipLaunchKernelGGL((k_fft_first16<INV, false>), dim3((unsigned)(N / 4096)), dim3(256),
+                             0, s, in, out, N, PackedIn{});
+        else
+          hipLaunchKernelGGL((k_fft_pass<16, INV>), grid, dim3(256), 0, s, in, out, N, Ns);
+        break;
+      default:  // 256: 16 consecutive j per workgroup
+        hipLaunchKernelGGL((k_fft_pass256<INV>), dim3((unsigned)(N / 4096)), dim3(256), 0, s, in,
+                           out, N, Ns);
     }
     Ns *= (uint64_t)R;
     cplx* t = in;
     in = out;
     out = t;
   };
+  // radix 2/4/8 first when log2 N is not a multiple of 4, then radix 16 (so
+  // that Ns >= 16), then radix 256 while 8 or more levels remain
   if (log % 4) pass(1 << (log % 4));
-  for (int p = 0; p < log / 4; ++p) pass(16);
+  int rem = log - log % 4;
+  if (rem >= 4) {
+    pass(16);
+    rem -= 4;
+  }
+  for (; rem >= 8; rem -= 8) pass(256);
+  if (rem == 4) pass(16);
   *result = in;
   return hipGetLastError();
 }
@@ -233,17 +363,16 @@ hipError_t fft64_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_b
   if (N > FFT64_MAX_LENGTH) return hipErrorInvalidValue;
   cplx* A = reinterpret_cast<cplx*>(work);
   cplx* B = A + N;
-  const dim3 g((unsigned)((N + 255) / 256));
+  const PackedIn pk{seed_bits, n + m - 1, x_bits, n, err};
   prof_begin(KID_FFT64, s);
-  hipLaunchKernelGGL(k_fft_pack, g, dim3(256), 0, s, seed_bits, n + m - 1, x_bits, n, A, N, err);
   cplx* Z = nullptr;
-  hipError_t e = transform<false>(A, B, N, s, &Z);
+  hipError_t e = transform<false>(A, B, N, &pk, s, &Z);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_fft_product, dim3((unsigned)((N / 2 + 1 + 255) / 256)), dim3(256), 0, s,
                        Z, N);
     cplx* other = Z == A ? B : A;
     cplx* K = nullptr;
-    e = transform<true>(Z, other, N, s, &K);
+    e = transform<true>(Z, other, N, nullptr, s, &K);
     if (e == hipSuccess)
       hipLaunchKernelGGL(k_fft_bits, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, K, N, n,
                          m, y, err);

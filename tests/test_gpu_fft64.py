@@ -50,7 +50,9 @@ def ref_hash(xw, n, sw, m):
 SIZES = [(1, 1), (2, 1), (5, 3), (31, 17), (64, 64), (65, 1), (100, 100), (1000, 625),
          (4095, 4000), (4096, 2560), (10007, 5003), (65536, 40960), (200003, 100001),
          (1 << 20, 655360),
-         # n+m-1 just above 2^24: a 2^25-point transform (radix 2 first, six of 16)
+         # transform lengths 2^12, 2^16, 2^20: the first forward pass reads the bits
+         (2560, 1537), (40000, 25537), (600000, 448577),
+         # n+m-1 just above 2^24: a 2^25-point transform (radix 2, 16, 256, 256, 16)
          (8388609, 8388609)]
 
 
