@@ -101,6 +101,32 @@ def algorithmic_work(kernel, n, m, batch=1):
     return None, None
 
 
+def ntt_pass_bytes(kernel, n, m, batch=1):
+    """Algorithmic HBM bytes of one launch of an NTT pass (4-byte residues):
+    pass A reads the n/8 raw bytes and writes Nc residues per raw chunk;
+    pass B reads them, reads one seed-spectrum window per chunk product and
+    writes Nc residues per output chunk; pass C reads those and writes the m/8
+    output bytes.  With one chunk each: n/8 + 4 Nc, 12 Nc, 4 Nc + m/8."""
+    p = ntt_plan(n, m)
+    Nc = 1 << p["log_nc"]
+    nx, ny = p["nx"], p["ny"]
+    prods = 3 if (nx, ny) == (2, 2) else nx * ny
+    if kernel == "ntt_cols_fwd":
+        return batch * (n // 8 + 4 * Nc * nx)
+    if kernel == "ntt_rows_hash":
+        return batch * 4 * Nc * (nx + prods + ny)
+    if kernel == "ntt_cols_inv":
+        return batch * (4 * Nc * ny + m // 8)
+    return None
+
+
+def hbm_roofline(kernel, nbytes, avg_s, traffic):
+    achieved = nbytes / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s", "frac": round(achieved * 1e9 / PEAK_HBM, 4), "traffic": traffic,
+            "kernel": kernel, "algorithmic_bytes": int(nbytes)}
+
+
 def roofline_for(kernel, work, unit, avg_s, traffic):
     if unit == "int32 mul":
         achieved = work / avg_s / 1e12
@@ -156,7 +182,7 @@ def cpu_paper_method(xw, n, sw, m):
     assert len(k) == m
     return {"value": round(n / dt / 1e9, 5), "unit": "Gbit/s", "seconds": round(dt, 3),
             "kind": "oracle (float64 FFT, the paper's method)", "cores": 1,
-            "sample": "the whole n = 2^23 block"}
+            "sample": "the whole n = 2^23 block"}, oracle.pack_bits(k)
 
 
 def cpu_baseline(xw, n, sw, m, seconds=12.0):
@@ -216,7 +242,11 @@ def single_transform_modmuls(n, m):
 def bench_uneven(ctx, q, torch, qi, reps=10):
     """4096 uneven blocks (n log-uniform in [2^14, 2^20], 64 seeds), each with
     its own min-entropy estimate and output length, as one plan (HIP graph
-    replay after the launch shapes are tuned)."""
+    replay after the launch shapes are tuned).  The same 4096 blocks are also
+    run as 4096 plain single-block calls (qrng_extract: estimate, m and hash
+    of one block), eagerly and captured in one HIP graph, on the same inputs;
+    `raw_vs_plain` divides the plan's rate by the faster of the two.  The
+    plan's output is checked against the plain calls' bit for bit."""
     import numpy as np
     cfg = qi.config(3)
     pool = qi.batched_pool(cfg)
@@ -227,7 +257,8 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
     for b in range(len(ns)):
         rows.append((int(offs[b]) // 8, int(ns[b]), int(ns[b]), yo, sids[pool["seed_of"][b]]))
         yo += (int(ns[b]) + 63) // 64
-    x = _dev_words(torch, qi.samples_as_words(pool["samples"]))
+    s_dev = torch.from_numpy(pool["samples"]).to("cuda:0")
+    x = s_dev.view(torch.int64)
     y = torch.empty(yo, dtype=torch.int64, device="cuda:0")
     m_out = torch.zeros(len(ns), dtype=torch.int64, device="cuda:0")
     out = {"workload": cfg["name"], "blocks": len(ns), "raw_bits": int(ns.sum())}
@@ -247,16 +278,68 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
         prof = ctx.profile_read()
         ctx.profile(False)
         eager.close()
+        plan.execute()
+        torch.cuda.synchronize()
         plan.close()
+        got, got_m = y.cpu().numpy(), m_out.cpu().numpy()
+
+        # the same blocks, one plain single-block call each
+        y_p = torch.empty(yo, dtype=torch.int64, device="cuda:0")
+        m_p = torch.zeros(len(ns), dtype=torch.int64, device="cuda:0")
+        blk = [(s_dev[int(offs[b]):int(offs[b]) + int(ns[b]) // 8], rows[b][4], int(ns[b]),
+                y_p[rows[b][3]:rows[b][3] + (int(ns[b]) + 63) // 64], m_p[b:b + 1])
+               for b in range(len(ns))]
+
+        def plain_all():
+            for sb, sid, n, yb, mb in blk:
+                ctx.extract(sb, sid, n, y=yb, m_out=mb)
+
+        # host-side cost of 4096 calls: wall clock around the whole sequence
+        plain_all()
+        torch.cuda.synchronize()
+        tp = []
+        for _ in range(3):
+            t1 = time.perf_counter()
+            plain_all()
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t1)
+        t_plain_eager = sorted(tp)[1]
+        # device-side cost: the 4096 calls captured once and replayed
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plain_all()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plain_all()
+        t_plain_graph = _time_fn(torch, g.replay, 5)
+        torch.cuda.synchronize()
+        plain, plain_m = y_p.cpu().numpy(), m_p.cpu().numpy()
+        del g
+        bad = [b for b in range(len(ns))
+               if plain_m[b] != got_m[b] or not np.array_equal(
+                   got[rows[b][3]:rows[b][3] + (int(ns[b]) + 63) // 64],
+                   plain[rows[b][3]:rows[b][3] + (int(ns[b]) + 63) // 64])]
+        out["verified_vs_plain_calls"] = not bad
+        if bad:
+            out["mismatched_blocks"] = bad[:16]
+
         # roofline-weighted fraction: each block's time at the int32-multiply
         # peak (3 multiplies per modular product) and the estimate's bytes at
         # the HBM peak, summed, over the measured step
         t_roof = sum(3.0 * single_transform_modmuls(int(b), int(b)) for b in ns) / PEAK_INT32_MUL
         t_roof += float(ns.sum()) / 8.0 / PEAK_HBM
         out["roofline_weighted_frac"] = round(t_roof / t, 4)
+        t_best_plain = min(t_plain_eager, t_plain_graph)
         out.update({"ms_per_step": round(t * 1e3, 4), "raw_gbps": round(ns.sum() / t / 1e9, 3),
                     "extracted_gbps": round(m_tot / t / 1e9, 3),
                     "eager_ms_per_step": round(te * 1e3, 4),
+                    "plain_calls_ms": {"eager_wall": round(t_plain_eager * 1e3, 3),
+                                       "graph_replay": round(t_plain_graph * 1e3, 3)},
+                    "plain_calls_raw_gbps": round(ns.sum() / t_best_plain / 1e9, 3),
+                    "raw_vs_plain": round(t_best_plain / t, 3),
                     "classes": info["classes"], "launch_groups": info["launches"],
                     "workspace_MiB": round(info["workspace_bytes"] / 2 ** 20, 1),
                     "kernels_ms": {k: round(ms, 4) for k, (c, ms) in prof.items()},
@@ -347,13 +430,15 @@ def bench_fft64(ctx, q, torch, qi, reps=10):
     y = torch.empty((m + 63) // 64, dtype=torch.int64, device="cuda:0")
     err = torch.zeros(1, dtype=torch.float64, device="cuda:0")
     t_f = _time_fn(torch, lambda: ctx.hash_fft64(x, n, sd, m, y=y, err_out=err), reps)
+    y_f = y.clone()
     t_n = _time_fn(torch, lambda: ctx.hash(x, n, sd, m, y=y, path=q.PATH_NTT), reps)
+    same = bool(torch.equal(y_f, y))
     N, b = fft64_stream_bytes(n, m)
     return {"workload": cfg["name"], "n": n, "m": m, "transform_length": N,
             "fft64_raw_gbps": round(n / t_f / 1e9, 3), "fft64_ms": round(t_f * 1e3, 4),
             "max_rounding_distance": float(err.item()),
             "ntt_seed_each_call_raw_gbps": round(n / t_n / 1e9, 3),
-            "ntt_vs_fft64": round(t_f / t_n, 3),
+            "ntt_vs_fft64": round(t_f / t_n, 3), "verified_equal_to_ntt": same,
             "fft64_roofline": {"bound": "hbm", "achieved": round(b / t_f / 1e9, 1),
                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                "frac": round(b / t_f / PEAK_HBM, 4),
@@ -417,12 +502,19 @@ def bench_sweep(ctx, q, torch, qi, reps=3):
         yw = (m + 63) // 64
         y = torch.empty(B * yw, dtype=torch.int64, device="cuda:0")
         row = {}
+        first = None
+        agree = True
         for name, path in (("auto", q.PATH_AUTO), ("ntt", q.PATH_NTT), ("mfma", q.PATH_MFMA),
                            ("direct", q.PATH_DIRECT)):
             if name in ("mfma", "direct") and lg > 14:
                 continue
             t = _time_fn(torch, lambda: ctx.hash_strided(x, n, n // 64, sid, m, y, yw, B,
                                                           path=path), reps)
+            # every timed path must give the same bits for every block
+            if first is None:
+                first = y.clone()
+            else:
+                agree = agree and bool(torch.equal(first, y))
             row[name] = round(tot / t / 1e9, 2)
             if name == "mfma":
                 # the dense int8 product: 2 m n operations per block
@@ -431,8 +523,11 @@ def bench_sweep(ctx, q, torch, qi, reps=3):
                                         "peak": PEAK_INT8 / 1e15, "unit": "POP/s int8",
                                         "frac": round(pops * 1e15 / PEAK_INT8, 4)}
         ctx.unregister_seed(sid)
+        row["paths_agree"] = agree
         res["2^%d" % lg] = row
-    return {"workload": cfg["name"], "unit": "raw Gbit/s", "by_block_bits": res}
+        del first
+    return {"workload": cfg["name"], "unit": "raw Gbit/s", "by_block_bits": res,
+            "verified_paths_agree": all(r["paths_agree"] for r in res.values())}
 
 
 def bench_serve(ctx, q, torch, qi, seconds=0.6, nwin=4, min_requests=10000):
@@ -629,8 +724,35 @@ def main():
     cnt, tot_ms = prof[dom]
     avg_s = tot_ms / cnt / 1e3
     work, unit = algorithmic_work(dom, n if dom != "histogram" else S * 8, m)
-    roof = roofline_for(dom, work, unit, avg_s, measured_traffic(dom, cfg["name"]))
+    traffic = measured_traffic(dom, cfg["name"])
+    nbytes = ntt_pass_bytes(dom, n, m)
+    if nbytes:
+        # the transform is streamed through HBM: its roofline is the HBM one
+        roof = hbm_roofline(dom, nbytes, avg_s, traffic)
+        roof_alu = roofline_for(dom, work, unit, avg_s, traffic)
+    else:
+        roof = roofline_for(dom, work, unit, avg_s, traffic)
+        roof_alu = None
     roof["avg_us"] = round(avg_s * 1e6, 3)
+    # the whole step against the four-step estimate 16 Nt + (n + m)/8 bytes of
+    # one length-Nt transform (Nt = 2^ceil log2(n + m - 1))
+    Nt = 1 << (n + m - 2).bit_length()
+    step_bytes = 16 * Nt + (n + m) // 8
+    roof_step = {"bound": "hbm", "algorithmic_bytes": step_bytes,
+                 "achieved": round(step_bytes / (elapsed / args.steps) / 1e9, 1),
+                 "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                 "frac": round(step_bytes / (elapsed / args.steps) / PEAK_HBM, 4),
+                 "note": "16 Nt + (n+m)/8 bytes over the whole step"}
+
+    # the timed output, checked: against the direct product (an independent
+    # kernel) here, against the oracle in the CPU leg below
+    y_host = y_t.cpu().numpy().view(np.uint64)
+    mw = (m + 63) // 64
+    y_dir = ctx.hash_seeded(x_t, n, sid, m, path=q.PATH_DIRECT).cpu().numpy().view(np.uint64)
+    verified = {"vs_direct_path": bool(np.array_equal(y_host[:mw], y_dir[:mw])),
+                "tail_zero": bool(not y_host[mw:].any() and
+                                  not (int(y_host[mw - 1]) >> (m - 64 * (mw - 1))
+                                       if m % 64 else 0))}
 
     out = {
         "metric": "raw Gbit/s hashed bit-exact (one block, min-entropy + Toeplitz hash)",
@@ -652,6 +774,8 @@ def main():
         "kernels": kernels,
         "ms_per_step_with_kernel_events": round(elapsed_prof / args.steps * 1e3, 4),
         "roofline": roof,
+        "roofline_alu": roof_alu,
+        "roofline_step": roof_step,
     }
 
     if args.extras:
@@ -689,35 +813,49 @@ def main():
     # the kernels changed since it was taken)
     hbm = {}
     for k in ("ntt_cols_fwd", "ntt_rows_hash", "ntt_cols_inv"):
+        if k not in prof:
+            continue
+        c_, ms_ = prof[k]
+        avg = ms_ / c_ / 1e3
+        alg = ntt_pass_bytes(k, n, m)
+        hbm[k] = {"algorithmic_bytes": alg, "GB/s": round(alg / avg / 1e9, 1),
+                  "frac_of_8TB/s": round(alg / avg / PEAK_HBM, 4)}
         b = measured_traffic(k, cfg["name"])
-        if b and k in prof:
-            c_, ms_ = prof[k]
-            gbs = b / (ms_ / c_ / 1e3) / 1e9
-            hbm[k] = {"GB/s": round(gbs, 1), "frac_of_8TB/s": round(gbs * 1e9 / PEAK_HBM, 4),
-                      "bytes_per_launch": b}
+        if b:
+            hbm[k]["counter_bytes"] = b
+            hbm[k]["counter_GB/s"] = round(b / avg / 1e9, 1)
     out["ntt_hbm"] = hbm or None
     plain = value
     if args.uneven:
         out["uneven_4096"] = bench_uneven(ctx, q, torch, qi)
-        out["uneven_4096"]["raw_vs_plain"] = round(out["uneven_4096"]["raw_gbps"] / plain, 3)
+        out["uneven_4096"]["raw_vs_single_block_path"] = round(
+            out["uneven_4096"]["raw_gbps"] / plain, 3)
+        verified["uneven_plan_vs_plain_calls"] = out["uneven_4096"]["verified_vs_plain_calls"]
     if args.sweep:
         out["sweep_2^30"] = bench_sweep(ctx, q, torch, qi)
-        out["sweep_2^30"]["best_raw_vs_plain"] = {
+        out["sweep_2^30"]["best_raw_vs_single_block_path"] = {
             k: round(max(v for kk, v in row.items() if isinstance(v, float)) / plain, 3)
             for k, row in out["sweep_2^30"]["by_block_bits"].items()}
+        verified["sweep_paths_agree"] = out["sweep_2^30"]["verified_paths_agree"]
     if args.modified:
         out["modified_toeplitz"] = bench_modified(ctx, q, torch, qi)
     if args.fft64:
         out["paper_method_fft64"] = bench_fft64(ctx, q, torch, qi)
+        verified["fft64_equal_to_ntt"] = out["paper_method_fft64"]["verified_equal_to_ntt"]
     if args.estimator:
         out["estimator"] = bench_estimator(ctx, q, torch, qi)
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(xw, n, sw, m, args.cpu_seconds)
-        out["cpu_paper_method"] = cpu_paper_method(xw, n, sw, m)
+        out["cpu_paper_method"], k_oracle = cpu_paper_method(xw, n, sw, m)
+        verified["vs_oracle"] = bool(np.array_equal(y_host[:mw], k_oracle[:mw]))
     ctx.close()
+    out["verified"] = all(verified.values())
+    out["verification"] = verified
     print(json.dumps(out))
+    if not out["verified"]:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -241,9 +241,12 @@ def test_plan_rejects_bad_descriptors(torch, ctx):
 
 def test_uneven_workload_full_size(torch, ctx):
     """The 4096-block uneven workload (n log-uniform in [2^14, 2^20], 64
-    seeds, per-block estimate, output sized at n): every block's m against the
-    oracle's estimate, every short block in full and sampled rows of the rest
-    against the oracle, as one graph replay."""
+    seeds, per-block estimate, output sized at n), as one graph replay.
+    Every block's m against the oracle's estimate; every block bit for bit
+    against the plain single-block call on the same bits (same seed prefix,
+    same m) and against the direct product (an independent kernel); blocks
+    up to 2^15 bits in full and 12 rows of every larger block against the
+    oracle."""
     cfg = qi.config(3)
     log("uneven workload: generating")
     pool = qi.batched_pool(cfg)
@@ -268,24 +271,42 @@ def test_uneven_workload_full_size(torch, ctx):
         with ctx.plan(rows, x, y, m_out=m_out, estimate=True, graph=True) as pl:
             pl.execute()
             torch.cuda.synchronize()
-        log("uneven workload: checking")
         got_m = m_out.cpu().numpy()
         got = host(y)
+        log("uneven workload: estimates")
         refs, want_m = estimate_refs(pool["samples"], offs, ns, ns)
         for b in range(len(ns)):
             if not near_integer(refs[b]["h_mod"]):
                 assert got_m[b] == want_m[b], (b, got_m[b], want_m[b])
+        # the same blocks with the plan's m: one plain call per block, and the
+        # direct product over the whole batch
+        log("uneven workload: plain single-block calls")
+        rows_m = [(xo, n, int(got_m[b]), yo_b, sid) for b, (xo, n, _, yo_b, sid) in enumerate(rows)]
+        y_plain = torch.full((yo,), -1, dtype=torch.int64, device="cuda:0")
+        for (xo, n, m, yo_b, sid) in rows_m:
+            if m:
+                ctx.hash_seeded(x[xo:xo + (n + 63) // 64], n, sid, m,
+                                y=y_plain[yo_b:yo_b + (m + 63) // 64])
+        log("uneven workload: direct product")
+        y_dir = torch.full((yo,), -1, dtype=torch.int64, device="cuda:0")
+        ctx.hash_batched(rows_m, x, y_dir, path=1)
+        torch.cuda.synchronize()
+        plain, direct = host(y_plain), host(y_dir)
+        log("uneven workload: checking")
         rng = np.random.default_rng(11)
         for b in range(len(ns)):
             xo, n, cap, yo_b, sid = rows[b]
             m = int(got_m[b])
             blk = got[yo_b:yo_b + (cap + 63) // 64]
             assert not oracle.unpack_bits(blk, cap)[m:].any(), "block %d tail" % b
+            nw = (m + 63) // 64
+            assert np.array_equal(blk[:nw], plain[yo_b:yo_b + nw]), "block %d vs plain call" % b
+            assert np.array_equal(blk[:nw], direct[yo_b:yo_b + nw]), "block %d vs direct" % b
             if n <= (1 << 15):
                 want = oracle.toeplitz_packed(xw[xo:xo + n // 64], n, seeds[sid], m)
                 assert np.array_equal(blk[:len(want)], want), "block %d" % b
-            elif b % 16 == 0 and m:
-                r = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, 30)]))
+            elif m:
+                r = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, 10)]))
                 want = oracle.toeplitz_rows(xw[xo:xo + n // 64], n, seeds[sid], n + m - 1, r)
                 bits = oracle.unpack_bits(blk, m)
                 assert np.array_equal(bits[r], want), "block %d rows" % b
