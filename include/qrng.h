@@ -160,6 +160,25 @@ qrng_status qrng_toeplitz_hash(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
                                const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
                                int path, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * hash as qrng_toeplitz_hash (same arguments, bits and errors) with every
+ * intermediate buffer in a fixed scratch array of QRNG_NOALLOC_SCRATCH_BYTES
+ * per device, which the library holds until the process ends.  The call
+ * allocates nothing and creates nothing (no HIP events either, so
+ * qrng_profile_* does not see it).  Limits: the transform path needs
+ * 4 (nwin + 1) Nc bytes (one transform of Nc >= n+m-1 points: Nc <= 2^21,
+ * so n+m-1 <= 2^21), the direct path about n/8 bytes; QRNG_EINVAL beyond
+ * them, with nothing enqueued.  The matrix-core path uses no scratch.  Every
+ * call on one device -- from any context -- shares that device's array, and
+ * each call rewrites all of it that it reads: calls whose work overlaps in
+ * time on one device (different streams, or different host threads) race
+ * and must be ordered by the caller.  Enqueued on `stream`. */
+#define QRNG_NOALLOC_SCRATCH_BYTES (16u << 20)
+qrng_status qrng_toeplitz_hash_noalloc(qrng_ctx *ctx, const uint64_t *x_dev, uint64_t n,
+                                       const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
+                                       int path, void *stream);
+
 /* Register a seed of L bits for reuse.  The memory must stay unchanged and
  * allocated until qrng_seed_unregister or qrng_destroy; transform-domain
  * copies of it are computed on first use per block shape and cached. */

@@ -87,7 +87,7 @@ _lib = None
 # every symbol the header declares
 EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_minentropy", "qrng_minentropy_subset", "qrng_output_bits",
-           "qrng_toeplitz_hash",
+           "qrng_toeplitz_hash", "qrng_toeplitz_hash_noalloc",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
            "qrng_modified_toeplitz_hash", "qrng_modified_toeplitz_hash_seeded",
            "qrng_toeplitz_hash_fft64",
@@ -130,6 +130,8 @@ def load_library(path: str | None = None):
     lib.qrng_output_bits.restype = i32
     lib.qrng_toeplitz_hash.argtypes = [vp, vp, u64, vp, u64, vp, i32, vp]
     lib.qrng_toeplitz_hash.restype = i32
+    lib.qrng_toeplitz_hash_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, i32, vp]
+    lib.qrng_toeplitz_hash_noalloc.restype = i32
     lib.qrng_seed_register.argtypes = [vp, vp, u64, ctypes.POINTER(u32)]
     lib.qrng_seed_register.restype = i32
     lib.qrng_seed_unregister.argtypes = [vp, u32]

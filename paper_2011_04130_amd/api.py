@@ -133,6 +133,24 @@ class Context:
                                            _stream(torch, self.device, stream)))
         return y
 
+    def hash_noalloc(self, x, n: int, seed, m: int, y, path: int = PATH_AUTO, stream=None):
+        """As hash(), through the entry point that allocates nothing (its
+        intermediate buffers live in a fixed per-device scratch array); y is
+        required, since this call must not allocate either."""
+        torch = self._torch
+        xp = self._dev_tensor(x, "x")
+        sp = self._dev_tensor(seed, "seed")
+        if x.numel() * x.element_size() < _words(n) * 8:
+            raise ValueError("x holds fewer than n bits")
+        if m and seed.numel() * seed.element_size() < _words(n + m - 1) * 8:
+            raise ValueError("seed holds fewer than n+m-1 bits")
+        if y is None or y.numel() * y.element_size() < _words(m) * 8:
+            raise ValueError("y must hold ceil(m/64) words")
+        yp = self._dev_tensor(y, "y")
+        check(self._lib.qrng_toeplitz_hash_noalloc(self._h, xp, n, sp, m, yp, path,
+                                                   _stream(torch, self.device, stream)))
+        return y
+
     def register_seed(self, seed, L: int) -> int:
         sp = self._dev_tensor(seed, "seed")
         if seed.numel() * seed.element_size() < _words(L) * 8:

@@ -78,6 +78,13 @@ bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
 
 uint64_t words64(uint64_t bits) { return (bits + 63) / 64; }
 
+// Scratch of qrng_toeplitz_hash_noalloc: one copy per device, alive until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returned for the current device (qrng_ctx::noalloc).
+constexpr uint64_t kNoAllocWords = QRNG_NOALLOC_SCRATCH_BYTES / 4;
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
 // Restores the caller's current device on scope exit.
 struct DeviceGuard {
   int prev = -1;
@@ -116,6 +123,7 @@ struct qrng_ctx {
   unsigned long long* counts_dev = nullptr;
   uint32_t* hist_scratch = nullptr;           // partial histograms + ticket (zeroed once)
   unsigned long long* counts_host = nullptr;  // pinned
+  uint32_t* noalloc = nullptr;  // this device's copy of `scratch` (device address)
   qrng_me_result* me_dev = nullptr;           // qrng_extract's default result slot
   uint64_t* m_dev = nullptr;                  // and output-length slot
   std::map<uint32_t, Seed> seeds;
@@ -551,6 +559,15 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
     return fail(QRNG_EDEVICE, "context setup on device %d failed", device);
   }
   c->tw = TwTables{c->tw_fwd, c->tw_inv, c->tw_fwd + T, c->tw_inv + T, c->g_lo, c->g_hi};
+  // the allocation-free entry point's scratch: this device's address of the
+  // file-scope array (each device holds its own copy)
+  void* sp = nullptr;
+  const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+  if (se != hipSuccess || !sp) {
+    qrng_destroy(c);
+    return fail(QRNG_EDEVICE, "scratch symbol on device %d: %s", device, hipGetErrorString(se));
+  }
+  c->noalloc = static_cast<uint32_t*>(sp);
   *out = c;
   return QRNG_OK;
 }
@@ -639,6 +656,54 @@ qrng_status qrng_toeplitz_hash(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
   CtxScope cs(ctx);
   return hash_one(ctx, x, n, seed, nullptr, m, y, path, reinterpret_cast<hipStream_t>(stream),
                   1, 0, 0);
+}
+
+qrng_status qrng_toeplitz_hash_noalloc(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
+                                       const uint64_t* seed, uint64_t m, uint64_t* y, int path,
+                                       void* stream) {
+  qrng_status st = check_hash_args(ctx, x, n, seed, m, y, path);
+  if (st || m == 0) return st;
+  const int p = path == QRNG_PATH_AUTO ? choose_path(n, m) : path;
+  DeviceGuard g(ctx->device);
+  CtxScope off(nullptr);  // no timing events: this call creates nothing
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint32_t* const sc = ctx->noalloc;
+  if (p == QRNG_PATH_DIRECT) {
+    if (n + m - 1 >= (1ull << 34))
+      return fail(QRNG_EINVAL, "direct path: n + m - 1 must be below 2^34");
+    const uint64_t need = direct_work_words(n, 1);
+    if (need > kNoAllocWords)
+      return fail(QRNG_EINVAL, "no-alloc direct hash needs %llu scratch bytes, at most %llu",
+                  (unsigned long long)(need * 4), (unsigned long long)QRNG_NOALLOC_SCRATCH_BYTES);
+    // the reversal kernel rewrites every word the product reads (padding too)
+    HIP_TRY(direct_hash(reinterpret_cast<const uint32_t*>(x), n,
+                        reinterpret_cast<const uint32_t*>(seed), m, reinterpret_cast<uint32_t*>(y),
+                        sc, ctx->num_cus, s, 1, 0, 0, nullptr));
+    return QRNG_OK;
+  }
+  if (p == QRNG_PATH_NTT) {
+    NttPlan pl;
+    if (!ntt_make_plan(n, m, &pl))
+      return fail(QRNG_EUNSUPPORTED, "NTT path cannot hash n=%llu m=%llu", (unsigned long long)n,
+                  (unsigned long long)m);
+    const uint64_t work = ntt_work_elems(pl, 1), need = work + ntt_seed_elems(pl);
+    if (need > kNoAllocWords)
+      return fail(QRNG_EINVAL, "no-alloc NTT hash needs %llu scratch bytes, at most %llu",
+                  (unsigned long long)(need * 4), (unsigned long long)QRNG_NOALLOC_SCRATCH_BYTES);
+    // the seed windows go after the transform workspace; both are written in
+    // full before they are read, so nothing needs clearing
+    uint32_t* W = sc + work;
+    HIP_TRY(ntt_seed_spectra(pl, reinterpret_cast<const uint32_t*>(seed), n, m, n + m - 1, W, sc,
+                             ctx->tw, s));
+    HIP_TRY(ntt_hash(pl, reinterpret_cast<const uint32_t*>(x), n, m, W,
+                     reinterpret_cast<uint32_t*>(y), sc, 1, 0, 0, ctx->tw, s));
+    return QRNG_OK;
+  }
+  // the matrix-core product uses no scratch
+  HIP_TRY(mfma_hash(reinterpret_cast<const uint32_t*>(x), n,
+                    reinterpret_cast<const uint32_t*>(seed), m, reinterpret_cast<uint32_t*>(y), 1,
+                    0, 0, s));
+  return QRNG_OK;
 }
 
 qrng_status qrng_seed_register(qrng_ctx* ctx, const uint64_t* seed, uint64_t L,
