@@ -179,11 +179,18 @@ qrng_status qrng_toeplitz_hash_noalloc(qrng_ctx *ctx, const uint64_t *x_dev, uin
                                        const uint64_t *seed_dev, uint64_t m, uint64_t *y_dev,
                                        int path, void *stream);
 
-/* Register a seed of L bits for reuse.  The memory must stay unchanged and
- * allocated until qrng_seed_unregister or qrng_destroy; transform-domain
- * copies of it are computed on first use per block shape and cached. */
+/* Register a seed of L bits for reuse (Sec. III.B: the seed a_1 .. a_{n+m-1}
+ * is chosen once and applied to many raw blocks).  The memory must stay
+ * unchanged and allocated until qrng_seed_unregister or qrng_destroy.  The
+ * transform-domain copies of the seed's first 2^k bits, for every k from 10
+ * up to min(23, ceil(log2 L)) -- one per transform length a block with this
+ * seed can need -- are computed here, enqueued on `stream` after the caller's
+ * earlier work there (the copy that filled the seed, say), and the call waits
+ * for them; copies for blocks above 2^23 bits are computed on first use.
+ * *seed_id receives the lowest free id (ids are below 4096: QRNG_EBUSY when
+ * 4095 seeds are registered). */
 qrng_status qrng_seed_register(qrng_ctx *ctx, const uint64_t *seed_dev, uint64_t L,
-                               uint32_t *seed_id);
+                               uint32_t *seed_id, void *stream);
 qrng_status qrng_seed_unregister(qrng_ctx *ctx, uint32_t seed_id);
 
 /* As qrng_toeplitz_hash with a registered seed (its first n+m-1 bits). */
@@ -253,15 +260,48 @@ qrng_status qrng_toeplitz_hash_strided(qrng_ctx *ctx, const uint64_t *x_pool_dev
                                        uint64_t *y_pool_dev, uint64_t y_stride_words,
                                        uint32_t nblocks, int path, void *stream);
 
-/* Hash many blocks (Sec. III.E: a long raw sequence split into blocks) in one
- * enqueued batch.  `blocks_host` lists nblocks descriptors (host memory);
- * x_pool_dev / y_pool_dev are the raw and output pools the offsets refer to.
- * Each block's result equals qrng_toeplitz_hash_seeded on that block alone.
- * Blocks are grouped by shape class and path; `path` forces one path for all
- * (AUTO lets the plan choose per class). */
-qrng_status qrng_toeplitz_hash_batched(qrng_ctx *ctx, const qrng_block *blocks_host,
+/* Hash many blocks (Sec. III.E: a long raw sequence split into blocks, here
+ * of any lengths) whose descriptors are in DEVICE memory: the library never
+ * reads them on the host, so the descriptors may be written by earlier work on
+ * `stream` and the whole call may be captured in a HIP graph.  Block b is
+ * blocks_dev[b] (qrng_block: raw bits at word x_word_off of x_pool_dev, n
+ * bits; m output bits at word y_word_off of y_pool_dev, bits past m in its last
+ * word written as 0), hashed with the first n+m-1 bits of registered seed
+ * seed_ids_or_null[b] (device memory, nblocks entries) or, when that pointer
+ * is NULL, of blocks_dev[b].seed_id.  Each block's bits equal
+ * qrng_toeplitz_hash_seeded on that block alone.
+ * On the device each block is checked (flags 0, 0 < n < 2^31, m <= n, a
+ * registered seed of at least n+m-1 bits, n+m-1 <= 2^23 and no longer than
+ * the longest seed registered when the call was made), sorted by transform
+ * length and hashed on the transform path; a block that fails a check is
+ * skipped (its output untouched) and counted, see
+ * qrng_toeplitz_hash_batched_rejected; m == 0 blocks are skipped.  The
+ * caller guarantees that the offsets lie inside the pools and that outputs
+ * do not overlap each other or the raw pool.  path: QRNG_PATH_AUTO or
+ * QRNG_PATH_NTT (others: QRNG_EUNSUPPORTED; host-descriptor batches and
+ * plans offer every path).  The context keeps per-class item lists for
+ * nblocks blocks and a transform workspace of up to 4 GiB: the first call
+ * with more blocks, or after a longer seed was registered, allocates them;
+ * later calls allocate nothing.  Enqueued on `stream`. */
+qrng_status qrng_toeplitz_hash_batched(qrng_ctx *ctx, const qrng_block *blocks_dev,
                                        uint32_t nblocks, const uint64_t *x_pool_dev,
-                                       uint64_t *y_pool_dev, int path, void *stream);
+                                       const uint32_t *seed_ids_or_null, uint64_t *y_pool_dev,
+                                       int path, void *stream);
+
+/* Number of descriptors the context's last qrng_toeplitz_hash_batched call
+ * skipped as invalid (waits for `stream`, which must be the one that call
+ * used). */
+qrng_status qrng_toeplitz_hash_batched_rejected(qrng_ctx *ctx, uint32_t *count_host,
+                                                void *stream);
+
+/* As qrng_toeplitz_hash_batched with the descriptors in host memory
+ * (`blocks_host`, each block's own seed_id), checked on the host before
+ * anything is enqueued (EINVAL on the first bad one, overlapping outputs
+ * included).  Blocks are grouped by shape and seed; `path` forces one path
+ * for all (AUTO lets the library choose per group). */
+qrng_status qrng_toeplitz_hash_batched_host(qrng_ctx *ctx, const qrng_block *blocks_host,
+                                            uint32_t nblocks, const uint64_t *x_pool_dev,
+                                            uint64_t *y_pool_dev, int path, void *stream);
 
 /* ------------------------------------------------------------------ plans
  * An uneven batch fixed once and replayed (Sec. III.E: a raw sequence cut

@@ -91,7 +91,8 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_seed_register", "qrng_seed_unregister", "qrng_toeplitz_hash_seeded",
            "qrng_modified_toeplitz_hash", "qrng_modified_toeplitz_hash_seeded",
            "qrng_toeplitz_hash_fft64",
-           "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_strided", "qrng_extract",
+           "qrng_toeplitz_hash_batched", "qrng_toeplitz_hash_batched_rejected",
+           "qrng_toeplitz_hash_batched_host", "qrng_toeplitz_hash_strided", "qrng_extract",
            "qrng_plan_create", "qrng_plan_execute", "qrng_plan_query", "qrng_plan_destroy",
            "qrng_tune_export", "qrng_tune_import",
            "qrng_server_create", "qrng_server_feed", "qrng_server_submit",
@@ -132,7 +133,7 @@ def load_library(path: str | None = None):
     lib.qrng_toeplitz_hash.restype = i32
     lib.qrng_toeplitz_hash_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, i32, vp]
     lib.qrng_toeplitz_hash_noalloc.restype = i32
-    lib.qrng_seed_register.argtypes = [vp, vp, u64, ctypes.POINTER(u32)]
+    lib.qrng_seed_register.argtypes = [vp, vp, u64, ctypes.POINTER(u32), vp]
     lib.qrng_seed_register.restype = i32
     lib.qrng_seed_unregister.argtypes = [vp, u32]
     lib.qrng_seed_unregister.restype = i32
@@ -144,9 +145,13 @@ def load_library(path: str | None = None):
     lib.qrng_modified_toeplitz_hash.restype = i32
     lib.qrng_modified_toeplitz_hash_seeded.argtypes = [vp, vp, u64, u32, u64, vp, i32, vp]
     lib.qrng_modified_toeplitz_hash_seeded.restype = i32
-    lib.qrng_toeplitz_hash_batched.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp,
-                                               i32, vp]
+    lib.qrng_toeplitz_hash_batched.argtypes = [vp, vp, u32, vp, vp, vp, i32, vp]
     lib.qrng_toeplitz_hash_batched.restype = i32
+    lib.qrng_toeplitz_hash_batched_rejected.argtypes = [vp, ctypes.POINTER(u32), vp]
+    lib.qrng_toeplitz_hash_batched_rejected.restype = i32
+    lib.qrng_toeplitz_hash_batched_host.argtypes = [vp, ctypes.POINTER(Block), u32, vp, vp,
+                                                    i32, vp]
+    lib.qrng_toeplitz_hash_batched_host.restype = i32
     lib.qrng_toeplitz_hash_strided.argtypes = [vp, vp, u64, u64, u32, u64, vp, u64, u32, i32,
                                                vp]
     lib.qrng_toeplitz_hash_strided.restype = i32

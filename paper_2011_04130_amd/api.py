@@ -9,6 +9,8 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 from ._lib import (MODEL_FIT, MODEL_GIVEN, MODEL_QUANTUM, PATH_AUTO, PLAN_ESTIMATE, PLAN_GRAPH,
                    PLAN_TUNE, U_MODEL_ARGMAX, Block, MeOpts, MeResult, PlanInfo, QrngError, Served,
                    ServerCfg, ServerStats, check, kernel_names, load_library)
@@ -151,12 +153,16 @@ class Context:
                                                    _stream(torch, self.device, stream)))
         return y
 
-    def register_seed(self, seed, L: int) -> int:
+    def register_seed(self, seed, L: int, stream=None) -> int:
+        """Register L seed bits; their transforms are computed now, on
+        `stream` (torch's current stream by default), after the work that
+        filled the seed."""
         sp = self._dev_tensor(seed, "seed")
         if seed.numel() * seed.element_size() < _words(L) * 8:
             raise ValueError("seed holds fewer than L bits")
         sid = ctypes.c_uint32()
-        check(self._lib.qrng_seed_register(self._h, sp, L, ctypes.byref(sid)))
+        check(self._lib.qrng_seed_register(self._h, sp, L, ctypes.byref(sid),
+                                           _stream(self._torch, self.device, stream)))
         self._seeds[sid.value] = seed  # keep the memory alive while registered
         return sid.value
 
@@ -288,16 +294,49 @@ class Context:
         assert rec.dtype.itemsize == ctypes.sizeof(Block)
         return rec
 
-    def hash_batched(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
+    def block_records(self, blocks, x_pool, y_pool):
+        """qrng_block records of (x_word_off, n, m, y_word_off, seed_id) rows as
+        a uint8 device tensor, for hash_batched (offsets checked against the
+        pools here, on the host)."""
+        rec = self._block_records(blocks, x_pool, y_pool)
+        return self._torch.from_numpy(rec.view(np.uint8).copy()).to("cuda:%d" % self.device)
+
+    def hash_batched(self, blocks_dev, x_pool, y_pool, seed_ids=None, path: int = PATH_AUTO,
+                     stream=None):
+        """Blocks described in device memory (blocks_dev: uint8 tensor of
+        qrng_block records, e.g. from block_records; seed_ids: optional int32
+        device tensor of one seed id per block).  Graph-capturable."""
+        torch = self._torch
+        nb = blocks_dev.numel() * blocks_dev.element_size() // ctypes.sizeof(Block)
+        bp = self._dev_tensor(blocks_dev, "blocks_dev")
+        sp = None
+        if seed_ids is not None:
+            if seed_ids.numel() < nb or seed_ids.element_size() != 4:
+                raise ValueError("seed_ids holds fewer than one 32-bit id per block")
+            sp = self._dev_tensor(seed_ids, "seed_ids")
+        xp = self._dev_tensor(x_pool, "x_pool")
+        yp = self._dev_tensor(y_pool, "y_pool")
+        check(self._lib.qrng_toeplitz_hash_batched(self._h, bp, nb, xp, sp, yp, path,
+                                                   _stream(torch, self.device, stream)))
+        return y_pool
+
+    def batched_rejected(self, stream=None) -> int:
+        """Descriptors the last hash_batched call skipped as invalid."""
+        c = ctypes.c_uint32()
+        check(self._lib.qrng_toeplitz_hash_batched_rejected(
+            self._h, ctypes.byref(c), _stream(self._torch, self.device, stream)))
+        return int(c.value)
+
+    def hash_batched_host(self, blocks, x_pool, y_pool, path: int = PATH_AUTO, stream=None):
         """blocks: (k, 5) integer array or iterable of
-        (x_word_off, n, m, y_word_off, seed_id)."""
+        (x_word_off, n, m, y_word_off, seed_id), in host memory."""
         torch = self._torch
         rec = self._block_records(blocks, x_pool, y_pool)
         arr = rec.ctypes.data_as(ctypes.POINTER(Block))
         xp = self._dev_tensor(x_pool, "x_pool")
         yp = self._dev_tensor(y_pool, "y_pool")
-        check(self._lib.qrng_toeplitz_hash_batched(self._h, arr, len(rec), xp, yp, path,
-                                                   _stream(torch, self.device, stream)))
+        check(self._lib.qrng_toeplitz_hash_batched_host(self._h, arr, len(rec), xp, yp, path,
+                                                        _stream(torch, self.device, stream)))
         return y_pool
 
     # -- uneven batches fixed once ---------------------------------------------

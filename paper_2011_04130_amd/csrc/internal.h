@@ -125,6 +125,37 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
 // with columns of at least 2^7)
 bool ntt_fuses_estimate(const NttPlan& p);
 
+// ------------------------------------------- device-scheduled batches
+// Registered seeds as the device sees them: entry `id` of a table of
+// SEED_TABLE_CAP entries (ids 1 .. SEED_TABLE_CAP-1).  W[k] is the cached
+// one-transform spectrum of length 2^k (BATCH_MIN_LOG <= k <= the seed's
+// class), L == 0 marks a free id.
+constexpr int SEED_TABLE_CAP = 4096;
+constexpr int BATCH_MIN_LOG = 10, BATCH_MAX_LOG = 23;
+constexpr int BATCH_CLASSES = BATCH_MAX_LOG - BATCH_MIN_LOG + 1;
+constexpr int BATCH_REJECTED = BATCH_CLASSES;  // counts[] slot of skipped descriptors
+constexpr int BATCH_COUNTS = 16;
+struct DevSeed {
+  uint64_t L;
+  const uint32_t* W[BATCH_MAX_LOG + 1];
+};
+// Sorts nblocks descriptors (device memory) into per-class item lists
+// (list k - BATCH_MIN_LOG holds cap items at items + (k - BATCH_MIN_LOG) cap)
+// with their counts, after clearing the counts; descriptors that fail a check
+// are counted in counts[BATCH_REJECTED] and skipped, as are blocks longer
+// than 2^max_log (no class launch covers them).  seed_ids (nullable):
+// block b's seed id, replacing blocks[b].seed_id.
+hipError_t batch_classify(const qrng_block* blocks, uint32_t nblocks, const uint32_t* seed_ids,
+                          const DevSeed* table, NttItem* items, uint32_t cap, int max_log,
+                          uint32_t* counts, hipStream_t s);
+// Items [item0, item0 + grid_items) of one transform-length class whose
+// count is read on the device (items past it do nothing).  Workspace:
+// ntt_work_elems(p, grid_items).
+hipError_t ntt_hash_items_dev(const NttPlan& p, const uint32_t* x_pool, const NttItem* items,
+                              const uint32_t* count, uint32_t item0, int grid_items,
+                              uint32_t* y_pool, uint32_t* work, const TwTables& tw,
+                              hipStream_t s);
+
 // ------------------------------------------------------------- direct path
 // `batch` blocks sharing one seed: block z reads x_bits + z*x_stride_bits and
 // writes y_bits + z*y_stride_bits (strides multiples of 64).

@@ -254,6 +254,9 @@ struct ColFwdArgs {
   int log2, log_nc;
   uint32_t* out;  // item y = blockIdx.y at out + y * Nc
   const NttItem* items;  // non-null: item y is the raw block items[y] (nmap = 1)
+  // non-null: item y exists only while item0 + y < *count (read on the device)
+  const uint32_t* count;
+  uint32_t item0;
   // hg > 0: workgroups x < hg of item 0 count samples for the min-entropy
   // estimate instead (those of other items exit), the last of them runs it
   uint32_t hg;
@@ -296,6 +299,7 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(Col
     }
     return;
   }
+  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
   const int bx = blockIdx.x - a.hg;  // column block
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int32_t Nc = 1 << a.log_nc;
@@ -373,6 +377,8 @@ struct ColInvArgs {
   const uint64_t* m_dev;  // nullable: the valid output length, read on the device (<= m)
   const NttItem* items;   // non-null: item y writes items[y] (ny = 1)
   const uint64_t* m_arr;  // with items, nullable: valid length of item y at m_arr[blk]
+  const uint32_t* count;  // as in ColFwdArgs
+  uint32_t item0;
 };
 
 // valid output bits: the plan's m, or the smaller length computed on the device
@@ -387,6 +393,7 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColI
                                                                            TwTables tw) {
   constexpr int NS = cslots<LOG1, true>();
   __shared__ uint32_t lds[(1 << LOG1) * COLS];
+  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int lane = threadIdx.x & 63;
   const int32_t Nc = 1 << a.log_nc;
@@ -479,6 +486,8 @@ struct RowArgs {
   const uint64_t* m_dev;  // nullable, as in ColInvArgs
   const NttItem* items;   // hash with nx = ny = 1: item zy is items[zy] (raw block,
   const uint64_t* m_arr;  // seed spectrum, output and valid length m_arr[blk])
+  const uint32_t* count;  // as in ColFwdArgs
+  uint32_t item0;
 };
 
 // Threads of a row kernel: every thread owns GPT groups of the last round.
@@ -510,6 +519,7 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   const int lane = tid & 63;
   const int row = blockIdx.x;
   const int zy = blockIdx.y;
+  if (!SEED && a.count && a.item0 + zy >= *a.count) return;
   const int32_t Nc = 1 << a.log_nc;
   const NttItem* desc = SEED ? nullptr : (a.items ? a.items + zy : nullptr);
   // transposed twiddle tables (lane-contiguous loads) pay off up to 2^13-point
@@ -1145,6 +1155,50 @@ hipError_t ntt_hash_items(const NttPlan& p, const uint32_t* x_pool, const NttIte
   ci.items = items;
   ci.m_arr = m_arr;
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, count), tw, s);
+}
+
+hipError_t ntt_hash_items_dev(const NttPlan& p, const uint32_t* x_pool, const NttItem* items,
+                              const uint32_t* count, uint32_t item0, int grid_items,
+                              uint32_t* y_pool, uint32_t* work, const TwTables& tw,
+                              hipStream_t s) {
+  if (p.nx != 1 || p.ny != 1) return hipErrorInvalidValue;
+  if (grid_items <= 0) return hipSuccess;
+  items += item0;
+  RowArgs r{};
+  r.nx = r.ny = 1;
+  r.log_nc = p.log_nc;
+  r.y = y_pool;
+  r.bits = x_pool;
+  r.items = items;
+  r.count = count;
+  r.item0 = item0;
+  if (p.log1 == 0) return rows_l<1, true, false, true>(p.log2, r, dim3(1, grid_items), tw, s);
+  ColFwdArgs c{};
+  c.bits = x_pool;
+  c.nmap = 1;
+  c.log2 = p.log2;
+  c.log_nc = p.log_nc;
+  c.out = work;
+  c.items = items;
+  c.count = count;
+  c.item0 = item0;
+  hipError_t e = cols_fwd(p.log1, c, dim3((1u << p.log2) / COLS, grid_items), tw, s);
+  if (e != hipSuccess) return e;
+  r.in = work;
+  r.out = work;
+  e = rows_l<1, false, false, false>(p.log2, r, dim3(1u << p.log1, grid_items), tw, s);
+  if (e != hipSuccess) return e;
+  ColInvArgs ci{};
+  ci.in = work;
+  ci.ny = 1;
+  ci.log2 = p.log2;
+  ci.log_nc = p.log_nc;
+  ci.y = y_pool;
+  ci.by = (int64_t)1 << p.log_nc;
+  ci.items = items;
+  ci.count = count;
+  ci.item0 = item0;
+  return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, grid_items), tw, s);
 }
 
 }  // namespace qrng

@@ -78,6 +78,12 @@ bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
 
 uint64_t words64(uint64_t bits) { return (bits + 63) / 64; }
 
+int ceil_log2_u64(uint64_t v) {
+  int k = 0;
+  while (k < 64 && (1ull << k) < v) ++k;
+  return k;
+}
+
 // Scratch of qrng_toeplitz_hash_noalloc: one copy per device, alive until the
 // process ends.  Host code never passes this name to a kernel (on the host it
 // is only a stand-in for the symbol); it uses the device address that
@@ -124,10 +130,17 @@ struct qrng_ctx {
   uint32_t* hist_scratch = nullptr;           // partial histograms + ticket (zeroed once)
   unsigned long long* counts_host = nullptr;  // pinned
   uint32_t* noalloc = nullptr;  // this device's copy of `scratch` (device address)
+  // device-descriptor batches: the device's view of the seed registry, the
+  // per-class item lists with their counts, and the transform workspace
+  DevSeed* seed_table = nullptr;  // SEED_TABLE_CAP entries
+  NttItem* batch_items = nullptr;
+  uint32_t* batch_counts = nullptr;
+  uint32_t batch_cap = 0;
+  uint32_t* batch_work = nullptr;
+  uint64_t batch_work_bytes = 0;
   qrng_me_result* me_dev = nullptr;           // qrng_extract's default result slot
   uint64_t* m_dev = nullptr;                  // and output-length slot
-  std::map<uint32_t, Seed> seeds;
-  uint32_t next_seed = 1;
+  std::map<uint32_t, Seed> seeds;  // ids 1 .. SEED_TABLE_CAP - 1, lowest free id first
   std::set<qrng_plan*> plans;
   std::set<qrng_server*> servers;
   // autotuned launch shape per transform-length class: (log2 Nc, ceil log2
@@ -548,6 +561,8 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
             hipMalloc(&c->hist_scratch, hist_scratch_words() * 4) == hipSuccess &&
             hipMemset(c->hist_scratch, 0, hist_scratch_words() * 4) == hipSuccess &&
             hipMalloc(&c->me_dev, sizeof(qrng_me_result)) == hipSuccess &&
+            hipMalloc(&c->seed_table, SEED_TABLE_CAP * sizeof(DevSeed)) == hipSuccess &&
+            hipMemset(c->seed_table, 0, SEED_TABLE_CAP * sizeof(DevSeed)) == hipSuccess &&
             hipMalloc(&c->m_dev, 8) == hipSuccess &&
             hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMemcpy(c->tw_fwd, f.data(), 2 * T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
@@ -590,6 +605,10 @@ void qrng_destroy(qrng_ctx* c) {
   if (c->counts_dev) (void)hipFree(c->counts_dev);
   if (c->hist_scratch) (void)hipFree(c->hist_scratch);
   if (c->me_dev) (void)hipFree(c->me_dev);
+  if (c->seed_table) (void)hipFree(c->seed_table);
+  if (c->batch_items) (void)hipFree(c->batch_items);
+  if (c->batch_counts) (void)hipFree(c->batch_counts);
+  if (c->batch_work) (void)hipFree(c->batch_work);
   if (c->m_dev) (void)hipFree(c->m_dev);
   if (c->counts_host) (void)hipHostFree(c->counts_host);
   delete c;
@@ -707,12 +726,58 @@ qrng_status qrng_toeplitz_hash_noalloc(qrng_ctx* ctx, const uint64_t* x, uint64_
 }
 
 qrng_status qrng_seed_register(qrng_ctx* ctx, const uint64_t* seed, uint64_t L,
-                               uint32_t* seed_id) {
+                               uint32_t* seed_id, void* stream) {
   if (!ctx || !seed || !seed_id) return fail(QRNG_EINVAL, "null argument");
   if (!aligned8(seed)) return fail(QRNG_EINVAL, "seed must be 8-byte aligned");
   if (L == 0) return fail(QRNG_EINVAL, "empty seed");
-  const uint32_t id = ctx->next_seed++;
-  ctx->seeds[id] = Seed{seed, L, 0, {}};
+  uint32_t id = 1;
+  for (auto& kv : ctx->seeds) {
+    if (kv.first != id) break;
+    ++id;
+  }
+  if (id >= (uint32_t)SEED_TABLE_CAP)
+    return fail(QRNG_EBUSY, "%d seeds are registered already", SEED_TABLE_CAP - 1);
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Seed sd{seed, L, 0, {}};
+  // one-transform spectra of every length 2^k the seed can serve, computed
+  // now on `stream` (after the caller's earlier work there, which may have
+  // written the seed): device-descriptor batches look them up on the device
+  DevSeed ds{};
+  ds.L = L;
+  const int top = std::min(BATCH_MAX_LOG, std::max(BATCH_MIN_LOG, ceil_log2_u64(L)));
+  qrng_status st = QRNG_OK;
+  for (int k = BATCH_MIN_LOG; k <= top && st == QRNG_OK; ++k) {
+    NttPlan p;
+    if (!ntt_plan_for_length(k, &p)) {
+      st = fail(QRNG_EUNSUPPORTED, "no transform of length 2^%d", k);
+      break;
+    }
+    uint32_t* W = nullptr;
+    if (hipMalloc(&W, ntt_seed_elems(p) * 4) != hipSuccess) {
+      st = fail(QRNG_ENOMEM, "seed spectrum of 2^%d points", k);
+      break;
+    }
+    sd.spectra[{0, 1ull << k}] = W;
+    st = ensure_work(ctx, ntt_work_elems(p, 1) + 1);
+    if (st) break;
+    const hipError_t e = ntt_seed_spectra(p, reinterpret_cast<const uint32_t*>(seed), 1, 1, L, W,
+                                          ctx->work, ctx->tw, s);
+    if (e != hipSuccess) st = fail(QRNG_EDEVICE, "seed spectrum: %s", hipGetErrorString(e));
+    ds.W[k] = W;
+  }
+  if (st == QRNG_OK) {
+    hipError_t e = hipMemcpyAsync(ctx->seed_table + id, &ds, sizeof ds, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(QRNG_EDEVICE, "seed registration: %s", hipGetErrorString(e));
+  }
+  if (st) {
+    (void)hipStreamSynchronize(s);
+    for (auto& sp : sd.spectra) (void)hipFree(sp.second);
+    return st;
+  }
+  ctx->seeds[id] = sd;
   *seed_id = id;
   return QRNG_OK;
 }
@@ -724,7 +789,9 @@ qrng_status qrng_seed_unregister(qrng_ctx* ctx, uint32_t seed_id) {
   if (it->second.plans)
     return fail(QRNG_EBUSY, "seed %u is used by %u live plan(s)", seed_id, it->second.plans);
   DeviceGuard g(ctx->device);
-  if (!it->second.spectra.empty()) HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipDeviceSynchronize());
+  const DevSeed zero{};
+  HIP_TRY(hipMemcpy(ctx->seed_table + seed_id, &zero, sizeof zero, hipMemcpyHostToDevice));
   for (auto& sp : it->second.spectra) (void)hipFree(sp.second);
   ctx->seeds.erase(it);
   return QRNG_OK;
@@ -886,9 +953,90 @@ qrng_status qrng_toeplitz_hash_strided(qrng_ctx* ctx, const uint64_t* x_pool, ui
   return QRNG_OK;
 }
 
-qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks,
+qrng_status qrng_toeplitz_hash_batched(qrng_ctx* ctx, const qrng_block* blocks_dev,
                                        uint32_t nblocks, const uint64_t* x_pool,
-                                       uint64_t* y_pool, int path, void* stream) {
+                                       const uint32_t* seed_ids_or_null, uint64_t* y_pool,
+                                       int path, void* stream) {
+  if (!ctx) return fail(QRNG_EINVAL, "null context");
+  if (nblocks == 0) return QRNG_OK;
+  if (!blocks_dev || !x_pool || !y_pool) return fail(QRNG_EINVAL, "null argument");
+  if (!aligned8(blocks_dev) || !aligned8(x_pool) || !aligned8(y_pool) ||
+      (reinterpret_cast<uintptr_t>(seed_ids_or_null) & 3u))
+    return fail(QRNG_EINVAL, "buffers must be aligned");
+  if (path < QRNG_PATH_AUTO || path > QRNG_PATH_MFMA) return fail(QRNG_EINVAL, "unknown path");
+  if (path != QRNG_PATH_AUTO && path != QRNG_PATH_NTT)
+    return fail(QRNG_EUNSUPPORTED,
+                "device descriptors run on the transform path (direct and matrix-core batches "
+                "take host descriptors)");
+  DeviceGuard g(ctx->device);
+  CtxScope cs(ctx);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // classes a block can fall in: up to the longest registered seed's
+  int top = BATCH_MIN_LOG;
+  for (auto& kv : ctx->seeds)
+    top = std::max(top, std::min(BATCH_MAX_LOG, ceil_log2_u64(kv.second.L)));
+  // item lists (grown to the batch size; a larger batch allocates once)
+  if (ctx->batch_cap < nblocks) {
+    HIP_TRY(hipDeviceSynchronize());
+    if (ctx->batch_items) (void)hipFree(ctx->batch_items);
+    if (ctx->batch_counts) (void)hipFree(ctx->batch_counts);
+    ctx->batch_items = nullptr;
+    ctx->batch_counts = nullptr;
+    ctx->batch_cap = 0;
+    if (hipMalloc(&ctx->batch_items, (uint64_t)BATCH_CLASSES * nblocks * sizeof(NttItem)) !=
+            hipSuccess ||
+        hipMalloc(&ctx->batch_counts, BATCH_COUNTS * 4) != hipSuccess)
+      return fail(QRNG_ENOMEM, "item lists for %u blocks", nblocks);
+    ctx->batch_cap = nblocks;
+  }
+  // transform workspace: every class of four-step length runs in rounds of
+  // as many items as it holds (at most 4 GiB, at least one item of the
+  // longest class); rounds past a class's count do nothing
+  const uint64_t want = std::min<uint64_t>(4ull << 30, (uint64_t)nblocks * (4ull << top));
+  const uint64_t need = std::max<uint64_t>(want, 4ull << top);
+  if (ctx->batch_work_bytes < need) {
+    HIP_TRY(hipDeviceSynchronize());
+    if (ctx->batch_work) (void)hipFree(ctx->batch_work);
+    ctx->batch_work = nullptr;
+    ctx->batch_work_bytes = 0;
+    if (hipMalloc(&ctx->batch_work, need) != hipSuccess)
+      return fail(QRNG_ENOMEM, "batch workspace of %llu bytes", (unsigned long long)need);
+    ctx->batch_work_bytes = need;
+  }
+  const uint32_t cap = ctx->batch_cap;
+  HIP_TRY(batch_classify(blocks_dev, nblocks, seed_ids_or_null, ctx->seed_table,
+                         ctx->batch_items, cap, top, ctx->batch_counts, s));
+  const uint32_t* xp = reinterpret_cast<const uint32_t*>(x_pool);
+  uint32_t* yp = reinterpret_cast<uint32_t*>(y_pool);
+  for (int k = BATCH_MIN_LOG; k <= top; ++k) {
+    NttPlan p;
+    if (!ntt_plan_for_length(k, &p)) return fail(QRNG_EUNSUPPORTED, "transform 2^%d", k);
+    const NttItem* list = ctx->batch_items + (uint64_t)(k - BATCH_MIN_LOG) * cap;
+    const uint32_t* cnt = ctx->batch_counts + (k - BATCH_MIN_LOG);
+    const uint64_t per = ntt_work_elems(p, 1) * 4;
+    const uint32_t round =
+        per ? (uint32_t)std::min<uint64_t>(nblocks, ctx->batch_work_bytes / per) : nblocks;
+    for (uint32_t i0 = 0; i0 < nblocks; i0 += round)
+      HIP_TRY(ntt_hash_items_dev(p, xp, list, cnt, i0, (int)std::min(round, nblocks - i0), yp,
+                                 ctx->batch_work, ctx->tw, s));
+  }
+  return QRNG_OK;
+}
+
+qrng_status qrng_toeplitz_hash_batched_rejected(qrng_ctx* ctx, uint32_t* count, void* stream) {
+  if (!ctx || !count) return fail(QRNG_EINVAL, "null argument");
+  *count = 0;
+  if (!ctx->batch_counts) return QRNG_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(count, ctx->batch_counts + BATCH_REJECTED, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return QRNG_OK;
+}
+
+qrng_status qrng_toeplitz_hash_batched_host(qrng_ctx* ctx, const qrng_block* blocks,
+                                            uint32_t nblocks, const uint64_t* x_pool,
+                                            uint64_t* y_pool, int path, void* stream) {
   if (!ctx) return fail(QRNG_EINVAL, "null context");
   if (nblocks == 0) return QRNG_OK;
   if (!blocks || !x_pool || !y_pool) return fail(QRNG_EINVAL, "null argument");

@@ -81,8 +81,10 @@ def test_null_context_is_rejected_without_device_work(lib):
     p = ctypes.cast(buf, ctypes.c_void_p)
     assert lib.qrng_toeplitz_hash(None, p, 64, p, 32, p, 0, None) == -1
     assert lib.qrng_toeplitz_hash_seeded(None, p, 64, 1, 32, p, 0, None) == -1
-    assert lib.qrng_toeplitz_hash_batched(None, None, 1, p, p, 0, None) == -1
-    assert lib.qrng_seed_register(None, p, 64, None) == -1
+    assert lib.qrng_toeplitz_hash_batched(None, p, 1, p, None, p, 0, None) == -1
+    assert lib.qrng_toeplitz_hash_batched_host(None, None, 1, p, p, 0, None) == -1
+    assert lib.qrng_toeplitz_hash_batched_rejected(None, None, None) == -1
+    assert lib.qrng_seed_register(None, p, 64, None, None) == -1
     assert lib.qrng_minentropy(None, p, 8, None, None, None, None) == -1
     lib.qrng_destroy(None)  # no-op
 

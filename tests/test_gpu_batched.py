@@ -54,7 +54,7 @@ def test_shared_seed_blocks_match_oracle(torch, ctx, n, m, nblk, path):
         blocks, xwords, ywords = strided_blocks(nblk, n, m, sid, y0=1)
         xw = qi.gen_bits(64 * xwords, nblk + n)
         yt = torch.full((ywords + 1,), -1, dtype=torch.int64, device="cuda:0")
-        ctx.hash_batched(blocks, dev(torch, xw), yt, path=path)
+        ctx.hash_batched_host(blocks, dev(torch, xw), yt, path=path)
         got = host(yt)
         assert got[0] == np.uint64(2 ** 64 - 1)          # untouched before the pool
         for (xo, bn, bm, yo, _) in blocks:
@@ -79,7 +79,7 @@ def test_mfma_single_block_and_sweep_slice(torch, ctx):
         outs = {}
         for path in (1, 2, 3):
             yt = torch.zeros(ywords, dtype=torch.int64, device="cuda:0")
-            ctx.hash_batched(blocks, xt, yt, path=path)
+            ctx.hash_batched_host(blocks, xt, yt, path=path)
             outs[path] = host(yt)
         assert np.array_equal(outs[1], outs[2]) and np.array_equal(outs[1], outs[3])
         for b in (0, 1, 511, 1023):

@@ -250,7 +250,7 @@ def test_seeded_and_batched_equal_single(torch, ctx):
         y_pool = torch.zeros(y_off + 4, dtype=torch.int64, device="cuda:0")
         for path in (0, 1, 2):
             y_pool.zero_()
-            ctx.hash_batched(blocks, xt, y_pool, path=path)
+            ctx.hash_batched_host(blocks, xt, y_pool, path=path)
             yp = host(y_pool)
             for (xo, n, m, yo, _) in blocks:
                 xb = xw[xo: xo + (n + 63) // 64]

@@ -244,7 +244,8 @@ def test_uneven_workload_full_size(torch, ctx):
     seeds, per-block estimate, output sized at n), as one graph replay.
     Every block's m against the oracle's estimate; every block bit for bit
     against the plain single-block call on the same bits (same seed prefix,
-    same m) and against the direct product (an independent kernel); blocks
+    same m), against the direct product (an independent kernel) and against
+    the batch call with device-resident descriptors; blocks
     up to 2^15 bits in full and 12 rows of every larger block against the
     oracle."""
     cfg = qi.config(3)
@@ -289,9 +290,13 @@ def test_uneven_workload_full_size(torch, ctx):
                                 y=y_plain[yo_b:yo_b + (m + 63) // 64])
         log("uneven workload: direct product")
         y_dir = torch.full((yo,), -1, dtype=torch.int64, device="cuda:0")
-        ctx.hash_batched(rows_m, x, y_dir, path=1)
+        ctx.hash_batched_host(rows_m, x, y_dir, path=1)
+        log("uneven workload: device descriptors")
+        y_dev = torch.full((yo,), -1, dtype=torch.int64, device="cuda:0")
+        ctx.hash_batched(ctx.block_records(rows_m, x, y_dev), x, y_dev)
+        assert ctx.batched_rejected() == 0
         torch.cuda.synchronize()
-        plain, direct = host(y_plain), host(y_dir)
+        plain, direct, devb = host(y_plain), host(y_dir), host(y_dev)
         log("uneven workload: checking")
         rng = np.random.default_rng(11)
         for b in range(len(ns)):
@@ -302,6 +307,7 @@ def test_uneven_workload_full_size(torch, ctx):
             nw = (m + 63) // 64
             assert np.array_equal(blk[:nw], plain[yo_b:yo_b + nw]), "block %d vs plain call" % b
             assert np.array_equal(blk[:nw], direct[yo_b:yo_b + nw]), "block %d vs direct" % b
+            assert np.array_equal(blk[:nw], devb[yo_b:yo_b + nw]), "block %d vs device batch" % b
             if n <= (1 << 15):
                 want = oracle.toeplitz_packed(xw[xo:xo + n // 64], n, seeds[sid], m)
                 assert np.array_equal(blk[:len(want)], want), "block %d" % b
