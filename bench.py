@@ -32,8 +32,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 P_NTT = 998244353
-PEAK_INT32_MUL = 39.3e12     # 256 CU x 64 lanes/clk x 2.4 GHz, full-rate v_mul_lo/hi_u32
-PEAK_BITOP = 78.6e12         # 2 x the above: simple 32-bit logic ops dual-issue (cf. fp32 157.3 TFLOP/s)
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for any
+# non-packed 32-bit VALU op (a wave64 instruction holds its SIMD 4 cycles);
+# the hardware counters confirm it for the three-input bit op of the direct
+# product (SQ_INSTS_VALU: 36.2 T lane-ops/s at 92 % VALU busy)
+PEAK_INT32_MUL = 39.3e12
+PEAK_BITOP = 39.3e12
 PEAK_HBM = 8.0e12
 PEAK_INT8 = 5.0e15           # dense int8 MFMA
 
@@ -617,6 +621,50 @@ def bench_serve(ctx, q, torch, qi, seconds=0.6, nwin=4, min_requests=10000):
     return res
 
 
+def bench_counters(ctx, q, torch, qi):
+    """A short fixed sequence for hardware-counter runs (rocprofv3 --pmc):
+    three qrng_extract steps on the n = 2^23 block (the three transform
+    passes), one direct product of that block, and one matrix-core pass over
+    the sweep's 2^30 bits at n = 2^12.  Prints the algorithmic work of each
+    launch, which the counter summaries divide by."""
+    import numpy as np
+    cfg = qi.config(1)
+    n, S = cfg["n"], cfg["S"]
+    samples = qi.gen_adc(S, cfg["sigma"], seed=cfg["adc_seed"])
+    s_t = torch.from_numpy(samples).to("cuda:0")
+    x_t = s_t.view(torch.int64)
+    sw = qi.gen_seed_words(2 * n - 1, cfg["seed_seed"])
+    sid = ctx.register_seed(_dev_words(torch, sw), 2 * n - 1)
+    y = torch.empty(n // 64, dtype=torch.int64, device="cuda:0")
+    m_t = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    for _ in range(3):
+        ctx.extract(s_t, sid, n, y=y, m_out=m_t)
+    torch.cuda.synchronize()
+    m = int(m_t.item())
+    ctx.hash_seeded(x_t, n, sid, m, y=y, path=q.PATH_DIRECT)
+    c2 = qi.config(2)
+    xs = torch.from_numpy(qi.gen_adc(c2["S"], c2["sigma"], seed=c2["adc_seed"])).to("cuda:0")
+    n2 = 1 << 12
+    m2 = n2 * c2["gamma_num"] // c2["gamma_den"]
+    B = c2["total_bits"] // n2
+    sid2 = ctx.register_seed(_dev_words(torch, qi.gen_seed_words(n2 + m2 - 1, 5)), n2 + m2 - 1)
+    y2 = torch.empty(B * (m2 // 64), dtype=torch.int64, device="cuda:0")
+    ctx.hash_strided(xs.view(torch.int64), n2, n2 // 64, sid2, m2, y2, m2 // 64, B,
+                     path=q.PATH_MFMA)
+    torch.cuda.synchronize()
+    ctx.unregister_seed(sid)
+    ctx.unregister_seed(sid2)
+    return {"extract_n2^23": {"n": n, "m": m, "launches": 3,
+                              "ntt_pass_bytes": {k: ntt_pass_bytes(k, n, m) for k in
+                                                 ("ntt_cols_fwd", "ntt_rows_hash",
+                                                  "ntt_cols_inv")},
+                              "int32_mul": {k: algorithmic_work(k, n, m)[0] for k in
+                                            ("ntt_cols_fwd", "ntt_rows_hash",
+                                             "ntt_cols_inv")}},
+            "direct_n2^23": {"n": n, "m": m, "gf2_macs": n * m, "bitops_32": n * m // 32},
+            "mfma_n2^12": {"n": n2, "m": m2, "blocks": B, "int8_ops": 2 * n2 * m2 * B}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -636,7 +684,7 @@ def main():
     ap.add_argument("--estimator", type=int, default=1,
                     help="also time the subset estimate and run the attacked-detector source")
     ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified", "fft64",
-                                       "estimator"],
+                                       "estimator", "counters"],
                     help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
@@ -666,7 +714,7 @@ def main():
         ctx = q.Context(0)
         fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve,
               "modified": bench_modified, "fft64": bench_fft64,
-              "estimator": bench_estimator}[args.only]
+              "estimator": bench_estimator, "counters": bench_counters}[args.only]
         print(json.dumps(fn(ctx, q, torch, qi)))
         ctx.close()
         return
