@@ -95,15 +95,27 @@ constexpr Tw16 make_tw16() {
   return t;
 }
 
+// a - b mod p in [0, 2p) for a, b in [0, 2p): a - b wraps to a large value
+// exactly when a < b, and then a - b + 2p is the one in range
+__device__ __forceinline__ uint32_t sub2(uint32_t a, uint32_t b) {
+  const uint32_t d = a - b;
+  return min(d, d + P2);
+}
+
 // In-register transform of R = 2, 4, 8 or 16 values.
 // Forward (INV = false): decimation in frequency, natural order in,
 //   bit-reversed order out: v[a'] = sum_a v[a] w_R^(a * bitrev(a')).
 // Inverse (INV = true): decimation in time, bit-reversed order in, natural
 //   order out, with w^-1 and no 1/R factor (the exact inverse times R).
-// Inputs in [0, 2p); outputs in [0, 2p).
-template <int R, bool INV>
+// Inputs in [0, 2p); outputs in [0, 2p), except with LAZY (forward only):
+// outputs 1 .. R-1 are left in [0, 4p), for a caller that multiplies each of
+// them by a twiddle next (a Shoup product takes any 32-bit input).  Inside
+// the inverse, a value whose next use is a twiddle product is left in
+// [0, 4p) for the same reason.
+template <int R, bool INV, bool LAZY = false>
 __device__ __forceinline__ void dft_reg(uint32_t (&v)[R]) {
   constexpr Tw16 T = make_tw16();
+  static_assert(!(INV && LAZY), "lazy outputs are a forward-transform option");
   if constexpr (!INV) {
 #pragma unroll
     for (int h = R / 2; h >= 1; h >>= 1) {
@@ -112,10 +124,13 @@ __device__ __forceinline__ void dft_reg(uint32_t (&v)[R]) {
         if (i & h) continue;
         const int j = i & (h - 1);       // i mod h
         const int e = j * (8 / h);       // w_{2h}^j = w_16^(j 16/(2h))
+        const bool lazy = LAZY && h == 1;  // last stage: outputs go to a twiddle
         uint32_t a = v[i], b = v[i + h];
-        v[i] = red2(a + b);
-        uint32_t d = a + P2 - b;
-        v[i + h] = (j == 0) ? red2(d) : mul_shoup(d, T.w[e], T.wq[e]);
+        v[i] = (lazy && i != 0) ? a + b : red2(a + b);
+        if (j != 0)
+          v[i + h] = mul_shoup(a + P2 - b, T.w[e], T.wq[e]);
+        else
+          v[i + h] = lazy ? a + P2 - b : sub2(a, b);
       }
     }
   } else {
@@ -128,8 +143,13 @@ __device__ __forceinline__ void dft_reg(uint32_t (&v)[R]) {
         const int e = j * (8 / h);
         uint32_t u = v[i];
         uint32_t t = (j == 0) ? v[i + h] : mul_shoup(v[i + h], T.iw[e], T.iwq[e]);
-        v[i] = red2(u + t);
-        v[i + h] = red2(u + P2 - t);
+        // output x feeds the next stage's twiddle product when that stage
+        // exists (2h <= R/2) and x is a multiplied operand there
+        const int H = 2 * h;
+        const bool mi = H <= R / 2 && (i & H) && (i & (H - 1));
+        const bool mh = H <= R / 2 && ((i + h) & H) && ((i + h) & (H - 1));
+        v[i] = mi ? u + t : red2(u + t);
+        v[i + h] = mh ? u + P2 - t : sub2(u, t);
       }
     }
   }

@@ -146,7 +146,8 @@ __device__ __forceinline__ void round_multi(int g0, int gstep, const uint2* __re
       }
       dft_reg<G::r, true>(v[u]);
     } else {
-      dft_reg<G::r, false>(v[u]);
+      // with twiddles to follow, outputs 1 .. r-1 may stay in [0, 4p)
+      dft_reg<G::r, false, (G::s > 1)>(v[u]);
       if constexpr (G::s > 1) {
         uint2 t[G::r];
         group_tw<G::r, G::s, TP>(tws + G::toff, (g0 + u * gstep) % G::s, t);
