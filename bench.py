@@ -56,7 +56,7 @@ def ntt_plan(n, m):
         k = 23
         B = 1 << 22
         nx, ny = -(-n // B), -(-m // B)
-    if k <= 14:
+    if k <= 15:
         l1, l2 = 0, k
     else:
         l2 = min(14, max(10, k - 9))

@@ -42,7 +42,9 @@ namespace qrng {
 
 namespace {
 
-constexpr int MAX_LOG_SUB = 14;  // longest in-LDS sub-transform
+constexpr int MAX_LOG_SUB = 15;    // longest in-LDS sub-transform (tables cover it)
+constexpr int MAX_LOG_ROW = 14;    // longest four-step row (two rows share one CU's LDS)
+constexpr int MAX_LOG_FUSED = 15;  // longest transform done whole by one workgroup
 
 // Offset of the (sub-length 2^lgR, radix 2^lgr) twiddle table.
 constexpr int tw_off(int lgR, int lgr) {
@@ -883,6 +885,10 @@ hipError_t rows_l(int log2, const RowArgs& a, dim3 grid, const TwTables& tw, hip
     case 12: return launch_rows<12, NX, IN_BITS, SEED, OUT_BITS>(a, grid, tw, s);
     case 13: return launch_rows<13, NX, IN_BITS, SEED, OUT_BITS>(a, grid, tw, s);
     case 14: return launch_rows<14, NX, IN_BITS, SEED, OUT_BITS>(a, grid, tw, s);
+    case 15:
+      // 2^15 points (139 KB of LDS) only as a whole transform in one workgroup
+      if constexpr (IN_BITS && NX == 1) return launch_rows<15, NX, IN_BITS, SEED, OUT_BITS>(a, grid, tw, s);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -966,12 +972,12 @@ bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* p) {
     if (p->nx > 4) return false;  // registers hold at most 4 raw chunks per row
   }
   const int k = p->log_nc;
-  if (k <= MAX_LOG_SUB) {
+  if (k <= MAX_LOG_FUSED) {
     p->log1 = 0;
     p->log2 = k;
   } else {
     int l2 = k - 9;
-    l2 = l2 < 10 ? 10 : (l2 > MAX_LOG_SUB ? MAX_LOG_SUB : l2);
+    l2 = l2 < 10 ? 10 : (l2 > MAX_LOG_ROW ? MAX_LOG_ROW : l2);
     p->log2 = l2;
     p->log1 = k - l2;
   }
