@@ -58,7 +58,8 @@ typedef enum {
 /* The set U over which the statistical distance is taken (Sec. II.C). */
 typedef enum {
   QRNG_U_MODEL_ARGMAX = 0, /* U = {argmax P}, the paper's chain of bounds */
-  QRNG_U_BOTH_ARGMAX = 1,  /* U = {argmax P, argmax P'} (never over-estimates) */
+  QRNG_U_BOTH_ARGMAX = 1,  /* U = {argmax P, argmax P'}, every value tied for the
+                              maximum of P included (never over-estimates) */
   QRNG_U_ALL = 2           /* U = all values: total-variation distance */
 } qrng_u_mode;
 

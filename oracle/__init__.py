@@ -56,7 +56,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-std=c99", "-o", tmp, src])
+                               "-std=c99", "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -77,6 +77,11 @@ def _load():
         lib.oracle_toeplitz_packed.argtypes = [u64p, ctypes.c_uint64, u64p,
                                                ctypes.c_uint64, u64p]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_minentropy_scalar.argtypes = [u64p, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_double)]
+        lib.oracle_minentropy_scalar.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -308,23 +313,28 @@ def minentropy_dists(P: np.ndarray, Pa: np.ndarray, N: int,
     I(G:E) = H_min - H'_min; d_U = (1/2) sum_{x in U} |P'(x) - P(x)|;
     Delta H_m = log2(d_U / 2^-(N+1) + 1) with N the ADC bits per sample;
     H_modify = H_min - Delta H_m.  U is the argmax of P by default (the
-    chain of inequalities replaces sum_U P by 2^-H_min), ties to the lowest
-    value (ties within TIE_REL relative).
+    chain of inequalities replaces sum_U P by 2^-H_min), the lowest value when
+    several share the maximum (within TIE_REL relative) -- the reading that
+    reproduces the worked example's Delta H_m of Sec. II.C, whose model has
+    two equal central bins.  U_BOTH_ARGMAX takes every value that shares the
+    maximum of P together with argmax P': the conservative set, whose d_U is
+    at least that of any one tied value.
     """
     P = np.asarray(P, dtype=np.float64)
     Pa = np.asarray(Pa, dtype=np.float64)
     pmax = float(P.max())
-    # lowest value whose model probability equals the maximum; values within
+    # values whose model probability equals the maximum; values within
     # TIE_REL of it count as equal (a model centred half way between two codes
     # gives two exactly equal bins, which rounding must not separate)
-    um = int(np.flatnonzero(P >= pmax * (1.0 - TIE_REL))[0])
+    tied = np.flatnonzero(P >= pmax * (1.0 - TIE_REL))
+    um = int(tied[0])
     ua = int(np.argmax(Pa))         # first maximum: lowest value on ties
     h_min = -math.log2(pmax)
     h_act = -math.log2(float(Pa[ua])) if Pa[ua] > 0 else float("inf")
     if u_mode == U_MODEL_ARGMAX:
         U = [um]
     elif u_mode == U_BOTH_ARGMAX:
-        U = sorted({um, ua})
+        U = sorted({*tied.tolist(), ua})
     elif u_mode == U_ALL:
         U = list(range(len(P)))
     else:
@@ -373,6 +383,26 @@ def minentropy_counts(counts: np.ndarray, N: int, mu: float | None = None,
     out["mu_hat"] = mu_hat
     out["sigma_hat"] = sigma_hat
     return out
+
+
+def minentropy_counts_scalar(counts: np.ndarray, N: int, mu: float | None = None,
+                             sigma: float | None = None,
+                             u_mode: int = U_MODEL_ARGMAX) -> dict:
+    """The same estimate from the C oracle's separate scalar-loop version
+    (its model CDF goes through erf instead of erfc); a cross-check of
+    ``minentropy_counts``, not a third reading."""
+    c = np.ascontiguousarray(counts, dtype=np.uint64)
+    assert len(c) == 1 << N
+    out = (ctypes.c_double * 8)()
+    given = mu is not None and sigma is not None
+    rc = _load().oracle_minentropy_scalar(_p(c, ctypes.c_uint64), N, int(given),
+                                          float(mu or 0.0), float(sigma or 0.0), u_mode, out)
+    if rc:
+        raise ValueError("no samples")
+    keys = ("mu_hat", "sigma_hat", "h_min", "h_actual", "d_u", "delta_h_m", "h_mod")
+    r = {k: float(out[i]) for i, k in enumerate(keys)}
+    r["argmax_model"] = int(out[7])
+    return r
 
 
 SPLITMIX_GAMMA = 0x9E3779B97F4A7C15

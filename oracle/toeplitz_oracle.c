@@ -109,3 +109,87 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Second, scalar-loop implementation of the min-entropy estimate of Sec. II
+ * (written apart from the numpy one, as a cross-check of it): from the 2^N
+ * counts of an N-bit ADC, the Gaussian model P (mean and population s.d. of
+ * the counts, or the given ones), H_min = -log2 max P, the statistical
+ * distance d_U = (1/2) sum_{x in U} |P'(x) - P(x)| with P' = counts / S,
+ * Delta H_m = log2(d_U 2^(N+1) + 1) and H_modify = H_min - Delta H_m.
+ * The model's bin v is Phi(v + 1/2) - Phi(v - 1/2) with Phi written through
+ * erf (the numpy route uses erfc); codes 0 and 2^N - 1 take the tails.
+ * U: 0 = the lowest value within 1e-9 (relative) of max P; 1 = every such
+ * value plus the lowest value of largest count; 2 = all values.
+ * out[0..7] = mu, sigma, h_min, h_actual, d_u, delta_h_m, h_mod,
+ * argmax_model.  Returns 0, or -1 when S = 0.
+ */
+#include <math.h>
+
+static double cdf_erf(double z) { return 0.5 * (1.0 + erf(z / sqrt(2.0))); }
+
+int oracle_minentropy_scalar(const uint64_t *counts, int N, int given, double mu_g,
+                             double sigma_g, int u_mode, double *out)
+{
+    const int K = 1 << N;
+    double S = 0.0, mu, sigma;
+    for (int v = 0; v < K; ++v) S += (double)counts[v];
+    if (!(S > 0.0)) return -1;
+    if (given) {
+        mu = mu_g;
+        sigma = sigma_g;
+    } else {
+        double s1 = 0.0, s2 = 0.0;
+        for (int v = 0; v < K; ++v) s1 += v * (double)counts[v];
+        mu = s1 / S;
+        for (int v = 0; v < K; ++v) {
+            const double d = v - mu;
+            s2 += d * d * (double)counts[v];
+        }
+        sigma = s2 > 0.0 ? sqrt(s2 / S) : 0.0;
+    }
+    double *P = (double *)malloc(sizeof(double) * K);
+    if (sigma > 0.0) {
+        for (int v = 0; v < K; ++v) {
+            const double hi = v == K - 1 ? 1.0 : cdf_erf((v + 0.5 - mu) / sigma);
+            const double lo = v == 0 ? 0.0 : cdf_erf((v - 0.5 - mu) / sigma);
+            P[v] = hi - lo;
+        }
+    } else {
+        double at = floor(mu + 0.5);
+        if (at < 0) at = 0;
+        if (at > K - 1) at = K - 1;
+        for (int v = 0; v < K; ++v) P[v] = v == (int)at ? 1.0 : 0.0;
+    }
+    double pmax = 0.0;
+    int ua = 0;
+    for (int v = 0; v < K; ++v) {
+        if (P[v] > pmax) pmax = P[v];
+        if (counts[v] > counts[ua]) ua = v;
+    }
+    int um = -1;
+    double d = 0.0;
+    for (int v = 0; v < K; ++v) {
+        const int tied = P[v] >= pmax * (1.0 - 1e-9);
+        if (tied && um < 0) um = v;
+        int in_u;
+        if (u_mode == 2) in_u = 1;
+        else if (u_mode == 1) in_u = tied || v == ua;
+        else in_u = 0;
+        if (in_u) d += fabs((double)counts[v] / S - P[v]);
+    }
+    if (u_mode == 0) d = fabs((double)counts[um] / S - P[um]);
+    d *= 0.5;
+    const double h_min = -log2(pmax);
+    const double delta = log2(d * pow(2.0, N + 1) + 1.0);
+    out[0] = mu;
+    out[1] = sigma;
+    out[2] = h_min;
+    out[3] = counts[ua] ? -log2((double)counts[ua] / S) : INFINITY;
+    out[4] = d;
+    out[5] = delta;
+    out[6] = h_min - delta;
+    out[7] = um;
+    free(P);
+    return 0;
+}

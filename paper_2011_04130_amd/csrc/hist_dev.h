@@ -158,17 +158,19 @@ __device__ void me_estimate(double cv, int N, int model, int u_mode, double mu_g
     P = (v == (int)at) ? 1.0 : 0.0;
   }
   // model argmax: lowest value within 1e-9 (relative) of max P, as on the
-  // host; observed argmax: the largest count, lowest value on ties
+  // host (the two-argmax set takes all of them); observed argmax: the
+  // largest count, lowest value on ties
   double pmax = v < K ? P : -1.0, cmax = v < K ? cv : -1.0;
   block_max2<NW>(pmax, cmax, red);
-  int um = v < K && P >= pmax * (1.0 - 1e-9) ? v : 1 << 30;
+  const bool tied = v < K && P >= pmax * (1.0 - 1e-9);
+  int um = tied ? v : 1 << 30;
   int ua = v < K && cv == cmax ? v : 1 << 30;
   block_min2<NW>(um, ua, redi);
   bool inU;
   if (u_mode == QRNG_U_MODEL_ARGMAX)
     inU = v == um;
   else if (u_mode == QRNG_U_BOTH_ARGMAX)
-    inU = v == um || v == ua;
+    inU = tied || v == ua;  // every value tied for max P, and argmax P'
   else
     inU = v < K;
   const double d = 0.5 * block_sum<NW>(inU ? fabs(cv / S - P) : 0.0, red);

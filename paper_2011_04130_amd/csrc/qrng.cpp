@@ -403,8 +403,9 @@ void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o
   if (o.u_mode == QRNG_U_MODEL_ARGMAX) {
     U.push_back(um);
   } else if (o.u_mode == QRNG_U_BOTH_ARGMAX) {
-    U.push_back(std::min(um, ua));
-    if (ua != um) U.push_back(std::max(um, ua));
+    // every value tied for the model's maximum, and the observed argmax
+    for (int v = 0; v < K; ++v)
+      if (P[v] >= pmax * (1.0 - kTieRel) || v == ua) U.push_back(v);
   } else {
     for (int v = 0; v < K; ++v) U.push_back(v);
   }

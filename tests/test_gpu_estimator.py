@@ -104,3 +104,40 @@ def test_attacked_detector_workload(torch, ctx, bits):
         close(me, ref)
         if u == q.U_BOTH_ARGMAX:
             assert me["h_mod"] <= observed + 1e-12
+
+
+@pytest.mark.parametrize("u_mode", [0, 1])
+def test_tied_model_bins_host_and_device(torch, ctx, u_mode):
+    """A given model centred half way between two codes (mu = 127.5) ties
+    bins 127 and 128: the default U is the lower one, the two-argmax set
+    both of them and argmax P'; host finish and device finish both agree
+    with the oracle."""
+    import ctypes
+
+    import paper_2011_04130_amd as q
+    from paper_2011_04130_amd._lib import MeResult
+    log("tied model bins u_mode=%d" % u_mode)
+    s = qi.gen_adc(1 << 17, 20.0, seed=43, mu=129.0)
+    ref = oracle.minentropy_counts(oracle.histogram(s, 8), 8, mu=127.5, sigma=20.0,
+                                   u_mode=u_mode)
+    assert ref["argmax_model"] == 127
+    st = torch.from_numpy(s).to("cuda:0")
+    me = ctx.minentropy(st, model=q.MODEL_GIVEN, mu=127.5, sigma=20.0, u_mode=u_mode)
+    close(me, ref)
+    assert me["argmax_model"] == 127
+    n = 8 * len(s)
+    sw = qi.gen_seed_words(2 * n - 1, 44)
+    sid = ctx.register_seed(torch.from_numpy(sw.view(np.int64).copy()).to("cuda:0"), 2 * n - 1)
+    try:
+        rs = ctypes.sizeof(MeResult)
+        me_out = torch.zeros(rs, dtype=torch.uint8, device="cuda:0")
+        m_out = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        ctx.extract(st, sid, n, m_out=m_out, me_out=me_out, model=q.MODEL_GIVEN, mu=127.5,
+                    sigma=20.0, u_mode=u_mode)
+        torch.cuda.synchronize()
+        dme = ctx.me_result_from_bytes(me_out)
+        close(dme, ref)
+        assert dme["argmax_model"] == 127
+        assert int(m_out.item()) == oracle.output_bits(n, 8, ref["h_mod"])
+    finally:
+        ctx.unregister_seed(sid)

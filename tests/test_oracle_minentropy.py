@@ -159,9 +159,11 @@ def test_single_block_workload_gives_81920():
     assert oracle.output_bits(c["n"], 8, r["h_mod"]) == c["m_expected"] == 81920
 
 
-def test_tie_between_model_bins_takes_lowest_value():
+def test_tie_between_model_bins():
     # a model mean half way between two codes makes their probabilities equal;
-    # rounding must not pick between them: the lowest value is U
+    # rounding must not pick between them.  The default U is the lowest tied
+    # value (the worked example's reading); the two-argmax set takes every
+    # tied value and argmax P', so its d_U is at least either tied bin's
     for mu in (120.5, 99.5, 200.5):
         P = oracle.gaussian_model(8, mu, 12.5)
         k = int(mu)
@@ -169,6 +171,40 @@ def test_tie_between_model_bins_takes_lowest_value():
         r = oracle.minentropy_dists(P, P, 8)
         assert r["argmax_model"] == k
         assert r["h_min"] == -math.log2(P.max())
+        for hi in (k, k + 1):
+            Pa = P.copy()
+            Pa[hi] += 1e-4
+            Pa[0] -= 1e-4
+            r = oracle.minentropy_dists(P, Pa, 8)
+            assert r["argmax_model"] == k
+            assert abs(r["d_u"] - (0.5e-4 if hi == k else 0.0)) < 1e-12
+            b = oracle.minentropy_dists(P, Pa, 8, oracle.U_BOTH_ARGMAX)
+            # U = {k, k+1} (argmax P' is the raised bin): its |P' - P| counts
+            assert abs(b["d_u"] - 0.5e-4) < 1e-12
+            assert b["h_mod"] <= r["h_mod"]
+
+
+def test_worked_example_tie_readings():
+    # the worked example's model (N(0, 1) over 32 bins of [-5, 5]) has two
+    # equal central bins: the lowest one reproduces the printed Delta H_m of
+    # 0.10; the other gives about 0.22, and the two-argmax set is at least that
+    g = json.load(open(os.path.join(GOLD, "worked_example.json")))
+    p = g["params"]
+    K = 1 << p["N"]
+    edges = p["lo"] + np.arange(K + 1) * (p["hi"] - p["lo"]) / K
+    cV = norm.cdf(edges)
+    cA = attacked_cdf(edges, p["alpha_e"], p["beta_e"], p["I_max"])
+    cV[0] = cA[0] = 0.0
+    cV[-1] = cA[-1] = 1.0
+    P, Pa = np.diff(cV), np.diff(cA)
+    tied = np.flatnonzero(P >= P.max() * (1 - oracle.TIE_REL))
+    assert tied.tolist() == [K // 2 - 1, K // 2]
+    r = oracle.minentropy_dists(P, Pa, p["N"])
+    assert r["argmax_model"] == K // 2 - 1 and 0.09 <= r["delta_h_m"] <= 0.13
+    other = math.log2(0.5 * abs(Pa[K // 2] - P[K // 2]) * 2 ** (p["N"] + 1) + 1)
+    assert 0.2 <= other <= 0.25
+    b = oracle.minentropy_dists(P, Pa, p["N"], oracle.U_BOTH_ARGMAX)
+    assert b["delta_h_m"] >= other
 
 
 def test_splitmix64_published_output_and_subset():
@@ -207,3 +243,36 @@ def test_classical_noise_subtraction():
         assert r["h_min"] < prev
         prev = r["h_min"]
     assert oracle.minentropy_counts(h, 8, sigma_classical=fit["sigma_hat"] + 1)["h_min"] == 0.0
+
+
+def _hist_cases():
+    rng = np.random.default_rng(90)
+    cases = []
+    for sigma in (8.0, 20.0, 40.0):
+        cases.append(oracle.histogram(qi.gen_adc(1 << 14, sigma, seed=int(sigma)), 8))
+    cases.append(oracle.histogram(qi.gen_adc(1 << 12, 20.0, seed=3, mu=250.0), 8))  # clipped
+    cases.append(rng.integers(0, 50, 256).astype(np.uint64))                      # arbitrary
+    z = np.zeros(256, dtype=np.uint64)
+    z[77] = 1000
+    cases.append(z)                                                               # point mass
+    cases.append(oracle.histogram(qi.gen_attack(1 << 14, 5, seed=4), 5))
+    return cases
+
+
+@pytest.mark.parametrize("u_mode", [0, 1, 2])
+def test_scalar_estimator_agrees_with_numpy(u_mode):
+    # Sec. II pin: the C oracle's separate scalar version (CDF through erf)
+    # agrees with the numpy estimator on fitted and given models, clipped,
+    # arbitrary, point-mass and attacked histograms, for every reading of U
+    for c in _hist_cases():
+        N = int(len(c)).bit_length() - 1
+        for kw in ({}, {"mu": 127.5, "sigma": 9.0} if N == 8 else {"mu": 15.5, "sigma": 3.0}):
+            a = oracle.minentropy_counts(c, N, u_mode=u_mode, **kw)
+            b = oracle.minentropy_counts_scalar(c, N, u_mode=u_mode, **kw)
+            assert a["argmax_model"] == b["argmax_model"]
+            for k in ("mu_hat", "sigma_hat", "h_min", "d_u", "delta_h_m", "h_mod"):
+                assert abs(a[k] - b[k]) <= 1e-12, (k, a[k], b[k])
+            if math.isinf(a["h_actual"]):
+                assert math.isinf(b["h_actual"])
+            else:
+                assert abs(a["h_actual"] - b["h_actual"]) <= 1e-12
