@@ -244,7 +244,11 @@ qrng_status qrng_modified_toeplitz_hash_seeded(qrng_ctx *ctx, const uint64_t *x_
  * m_dev / out_dev (nullable, device memory) receive m and the estimate
  * (qrng_me_result) when the stream reaches them.  The seed must have at
  * least n + m_cap - 1 bits.  Same estimate and bits as qrng_minentropy +
- * qrng_output_bits + qrng_toeplitz_hash_seeded. */
+ * qrng_output_bits + qrng_toeplitz_hash_seeded.  The partial histograms
+ * carry the call's tag and sample counts, checked before the estimate uses
+ * them: should a check ever fail, the call fails closed -- m = 0 (no output
+ * bits) and the estimate's fields NaN with samples = 0 -- rather than
+ * extract with an unchecked length (qrng_minentropy returns QRNG_EDEVICE). */
 qrng_status qrng_extract(qrng_ctx *ctx, const uint8_t *samples_dev, uint64_t S,
                          const qrng_me_opts *opts, double log2_inv_eps, uint32_t seed_id,
                          uint64_t m_cap, uint64_t *y_dev, uint64_t *m_dev,

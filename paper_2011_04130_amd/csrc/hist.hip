@@ -83,11 +83,15 @@ __global__ __launch_bounds__(256) void k_block_estimate(MeBatchArgs a) {
 }  // namespace
 
 uint64_t hist_scratch_words() { return TICKET_WORD + 64; }
+uint64_t hist_ticket_word() { return TICKET_WORD; }
 
 hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
                          unsigned long long* counts_out, const MeDevArgs* finish,
-                         hipStream_t s, uint64_t subset_seed, uint32_t keep_thr) {
+                         hipStream_t s, uint64_t subset_seed, uint32_t keep_thr,
+                         uint32_t epoch, uint32_t expect_xor) {
   HistArgs a{};
+  a.epoch = epoch;
+  a.expect = epoch ^ expect_xor;
   a.s = samples;
   a.S = S;
   a.N = N;

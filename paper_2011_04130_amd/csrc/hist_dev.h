@@ -15,6 +15,10 @@ namespace hd {
 
 constexpr int HB = 257;  // 256 values + out-of-range
 constexpr int PS = 260;  // row stride of the partial counts (16-byte rows)
+// two more words of a partial row: the call's tag, and the samples the
+// workgroup examined mod 2^32 (the finish checks both before it trusts the
+// rows)
+constexpr int ROW_TAG = 257, ROW_SEEN = 258;
 // the ticket of the fused estimate sits after the partial rows
 constexpr uint64_t TICKET_WORD = (uint64_t)HIST_MAX_GROUPS * PS;
 
@@ -247,6 +251,8 @@ struct HistArgs {
   unsigned long long* counts;   // nullable: the 2^N + 1 summed counts
   bool finish;                  // run the estimate (MeDevArgs below)
   MeDevArgs me;
+  uint32_t epoch;               // tag of this call, written into every partial row
+  uint32_t expect;              // tag the finish requires (epoch, except under fault tests)
 };
 
 // workgroups for S samples: about 16 KiB each, at most HIST_MAX_GROUPS (the
@@ -325,8 +331,12 @@ __device__ void hist_part_body(const HistArgs& a, uint32_t wg, uint32_t* h) {
   }
   __syncthreads();
   uint32_t* mine = a.part + (uint64_t)wg * PS;
+  // samples this workgroup examined (its vectors, and the ragged ends for
+  // workgroup 0): over all rows they add up to S
+  const uint64_t seen = (v1 > v0 ? v1 - v0 : 0) * 16 + (wg == 0 ? a.S - nvec * 16 : 0);
   for (int b = tid; b < PS; b += NT) {
-    const uint32_t v = b < HB ? merged<HCW>(h, b) : 0u;
+    const uint32_t v = b < HB ? merged<HCW>(h, b)
+                              : (b == ROW_TAG ? a.epoch : (b == ROW_SEEN ? (uint32_t)seen : 0u));
     if constexpr (COHERENT)
       __hip_atomic_store(mine + b, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
@@ -337,6 +347,9 @@ __device__ void hist_part_body(const HistArgs& a, uint32_t wg, uint32_t* h) {
 struct FinishLds {
   unsigned long long qs[4][256];
   unsigned long long oobs[64];
+  unsigned long long seen[64];
+  uint32_t bad[64];
+  uint32_t ok;
   double me[me_lds_doubles(512)];
 };
 
@@ -384,9 +397,33 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
       unsigned long long o = 0;
       for (uint64_t r = tid; r < G; r += 64) o += a.part[r * PS + 256];
       L.oobs[tid] = o;
+    } else if (tid < 128) {
+      // the rows' tags and examined-sample counts
+      unsigned long long sn = 0;
+      uint32_t bad = 0;
+      for (uint64_t r = tid - 64; r < G; r += 64) {
+        sn += a.part[r * PS + ROW_SEEN];
+        bad |= a.part[r * PS + ROW_TAG] ^ a.expect;
+      }
+      L.seen[tid - 64] = sn;
+      L.bad[tid - 64] = bad;
     }
   }
   __syncthreads();
+  if (tid == 0) {
+    unsigned long long sn = 0;
+    uint32_t bad = 0;
+    for (int r = 0; r < 64; ++r) {
+      sn += L.seen[r];
+      bad |= L.bad[r];
+    }
+    // every row carries this call's tag and together they examined every
+    // sample: otherwise a row is stale or missing, and the estimate fails
+    // closed (no output bits) instead of trusting it
+    L.ok = bad == 0 && (uint32_t)sn == (uint32_t)a.S;  // rows hold the counts mod 2^32
+  }
+  __syncthreads();
+  const bool ok = L.ok != 0;
   const uint64_t t = tid < 256 ? L.qs[0][tid] + L.qs[1][tid] + L.qs[2][tid] + L.qs[3][tid] : 0;
   if (a.counts) {
     if (tid < (int)lim) a.counts[tid] = t;
@@ -394,12 +431,23 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
       uint64_t o = 0;
       for (int r = 0; r < 64; ++r) o += L.oobs[r];
       a.counts[lim] = o;
+      a.counts[lim + 1] = ok ? 1u : 0u;
     }
   }
-  if (a.finish)
+  if (!a.finish) return;
+  if (ok) {
     me_estimate<NT>((double)t, a.N, a.me.model, a.me.u_mode, a.me.mu, a.me.sigma, a.me.n,
                     a.me.log2_inv_eps, a.me.m_cap, reinterpret_cast<qrng_me_result*>(a.me.out),
                     a.me.m_out, L.me);
+  } else if (tid == 0) {
+    qrng_me_result r;
+    const double nan = __builtin_nan("");
+    r.mu_hat = r.sigma_hat = r.h_min = r.h_actual = r.d_u = r.delta_h_m = r.h_mod = nan;
+    r.argmax_model = r.argmax_empirical = 0xffffffffu;
+    r.samples = 0;
+    if (a.me.out) *reinterpret_cast<qrng_me_result*>(a.me.out) = r;
+    if (a.me.m_out) *a.me.m_out = 0;
+  }
 }
 
 // One of a.G counting workgroups of a launch that also does other work: it
@@ -414,6 +462,29 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
 // invalidates its die's caches (device-scope acquire) before reading the
 // rows.  lds: at least max(HCW * HB words,
 // sizeof(FinishLds)) bytes, 16-byte aligned.
+// The ticket word holds (tag, count): TICKET_COUNT_BITS low bits count the
+// workgroups of the call with that tag.  A workgroup that finds another
+// call's tag there (one that never completed) starts the count afresh, so a
+// stuck ticket cannot silence later calls.
+constexpr int TICKET_COUNT_BITS = 9;  // HIST_MAX_GROUPS = 256 fits
+static_assert(HIST_MAX_GROUPS < (1 << TICKET_COUNT_BITS), "ticket count field");
+
+// Takes this workgroup's ticket; true for the last of the call's G.  Lock
+// free: a failed compare-and-swap means another workgroup's succeeded, so
+// the loop ends after at most G rounds.
+__device__ inline bool take_ticket(uint32_t* ticket, uint32_t epoch, uint32_t G) {
+  constexpr uint32_t CM = (1u << TICKET_COUNT_BITS) - 1;
+  const uint32_t tag = epoch << TICKET_COUNT_BITS;
+  uint32_t old = __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t k = 0; k <= G; ++k) {
+    const uint32_t cnt = (old & ~CM) == tag ? (old & CM) : 0u;
+    const uint32_t seen = atomicCAS(ticket, old, tag | (cnt + 1u));
+    if (seen == old) return cnt + 1u == G;
+    old = seen;
+  }
+  return false;  // not reached: at most G - 1 other workgroups can win first
+}
+
 template <int NT, int HCW>
 __device__ void estimate_workgroup(const HistArgs& a, uint32_t wg, uint32_t* ticket,
                                    uint32_t* lds) {
@@ -421,13 +492,14 @@ __device__ void estimate_workgroup(const HistArgs& a, uint32_t wg, uint32_t* tic
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) lds[0] = atomicAdd(ticket, 1u) == a.G - 1 ? 1u : 0u;
+  if (threadIdx.x == 0) lds[0] = take_ticket(ticket, a.epoch, a.G) ? 1u : 0u;
   __syncthreads();
   if (lds[0] == 0u) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
   hist_finish_body<NT>(a, *reinterpret_cast<FinishLds*>(lds));
-  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+  // count back to 0 under the same tag, for a replay of this launch
+  if (threadIdx.x == 0) atomicExch(ticket, a.epoch << TICKET_COUNT_BITS);
 }
 
 }  // namespace hd

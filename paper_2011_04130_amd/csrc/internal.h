@@ -115,6 +115,8 @@ struct EstJob {
   uint64_t S;
   uint32_t* scratch;
   MeDevArgs me;
+  uint32_t epoch;  // tag of this call (below 2^23; consecutive calls differ)
+  uint32_t expect_xor;  // nonzero only in fault tests: the finish expects another tag
 };
 hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64_t m,
                     const uint32_t* W, uint32_t* y_bits, uint32_t* work, int batch,
@@ -197,13 +199,18 @@ constexpr int HIST_MAX_GROUPS = 256;
 // ordered on one stream.
 uint64_t hist_scratch_words();
 // Two launches: histogram of S samples of N bits (N <= 8); counts_out
-// (nullable, device) receives the 2^N counts and then the number of samples
-// >= 2^N; with `finish` the estimate and m are written on the device.
-// S < 2^40.  keep_thr > 0: only the samples the seeded generator keeps count
-// (hist_dev.h, subset_keep).
+// (nullable, device) receives the 2^N counts, then the number of samples
+// >= 2^N, then 1 if the partial counts passed the finish's consistency check
+// (0: the estimate failed closed, m = 0); with `finish` the estimate and m
+// are written on the device.  S < 2^40.  keep_thr > 0: only the samples the
+// seeded generator keeps count (hist_dev.h, subset_keep).  epoch: tag of the
+// call (below 2^23), written into and checked on every partial row.
 hipError_t hist_estimate(const uint8_t* samples, uint64_t S, int N, uint32_t* scratch,
                          unsigned long long* counts_out, const MeDevArgs* finish,
-                         hipStream_t s, uint64_t subset_seed = 0, uint32_t keep_thr = 0);
+                         hipStream_t s, uint64_t subset_seed = 0, uint32_t keep_thr = 0,
+                         uint32_t epoch = 0, uint32_t expect_xor = 0);
+// word of the fused estimate's ticket in the histogram scratch
+uint64_t hist_ticket_word();
 
 // Per-block estimates of an uneven batch of 8-bit sample blocks (one
 // workgroup each): block b's histogram, estimate (out[b], nullable) and

@@ -1088,6 +1088,8 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
     c.est.counts = nullptr;
     c.est.finish = true;
     c.est.me = est->me;
+    c.est.epoch = est->epoch;
+    c.est.expect = est->epoch ^ est->expect_xor;
     c.hg = c.est.G;
     c.ticket = est->scratch + hd::TICKET_WORD;
   }

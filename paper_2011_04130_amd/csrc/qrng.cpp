@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -78,6 +79,22 @@ bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes) {
 
 uint64_t words64(uint64_t bits) { return (bits + 63) / 64; }
 
+// Test-only fault injection, read from the environment on every call:
+// QRNG_FAULT=launch makes the hash and estimate entry points fail with
+// QRNG_EDEVICE before they enqueue anything; =ticket leaves a stale ticket
+// (another call's tag, a partial count) before the fused estimate, as a
+// launch that never completed would; =rows makes the estimate's finish
+// expect another call's tag, so its consistency check fails.
+enum Fault { FAULT_NONE = 0, FAULT_LAUNCH, FAULT_TICKET, FAULT_ROWS };
+int fault_mode() {
+  const char* e = std::getenv("QRNG_FAULT");
+  if (!e) return FAULT_NONE;
+  if (!std::strcmp(e, "launch")) return FAULT_LAUNCH;
+  if (!std::strcmp(e, "ticket")) return FAULT_TICKET;
+  if (!std::strcmp(e, "rows")) return FAULT_ROWS;
+  return FAULT_NONE;
+}
+
 int ceil_log2_u64(uint64_t v) {
   int k = 0;
   while (k < 64 && (1ull << k) < v) ++k;
@@ -130,6 +147,7 @@ struct qrng_ctx {
   uint32_t* hist_scratch = nullptr;           // partial histograms + ticket (zeroed once)
   unsigned long long* counts_host = nullptr;  // pinned
   uint32_t* noalloc = nullptr;  // this device's copy of `scratch` (device address)
+  uint32_t est_epoch = 0;       // tag of the latest histogram call (below 2^23)
   // device-descriptor batches: the device's view of the seed registry, the
   // per-class item lists with their counts, and the transform workspace
   DevSeed* seed_table = nullptr;  // SEED_TABLE_CAP entries
@@ -304,6 +322,8 @@ qrng_status hash_one(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const uint64_
                      Seed* sd, uint64_t m, uint64_t* y, int path, hipStream_t s, int batch,
                      uint64_t xs, uint64_t ys, const uint64_t* m_dev = nullptr,
                      const EstJob* est = nullptr) {
+  if (fault_mode() == FAULT_LAUNCH)
+    return fail(QRNG_EDEVICE, "injected launch failure (QRNG_FAULT=launch)");
   if (path == QRNG_PATH_AUTO) path = choose_path(n, m);
   if (path == QRNG_PATH_DIRECT) return run_direct(ctx, x, n, seed, m, y, s, batch, xs, ys, m_dev);
   if (path == QRNG_PATH_NTT) {
@@ -558,14 +578,14 @@ qrng_status qrng_create(qrng_ctx** out, int device) {
             hipMalloc(&c->tw_inv, 2 * T * sizeof(uint2)) == hipSuccess &&
             hipMalloc(&c->g_lo, 4096 * 4) == hipSuccess &&
             hipMalloc(&c->g_hi, 2048 * 4) == hipSuccess &&
-            hipMalloc(&c->counts_dev, 257 * 8) == hipSuccess &&
+            hipMalloc(&c->counts_dev, 258 * 8) == hipSuccess &&
             hipMalloc(&c->hist_scratch, hist_scratch_words() * 4) == hipSuccess &&
             hipMemset(c->hist_scratch, 0, hist_scratch_words() * 4) == hipSuccess &&
             hipMalloc(&c->me_dev, sizeof(qrng_me_result)) == hipSuccess &&
             hipMalloc(&c->seed_table, SEED_TABLE_CAP * sizeof(DevSeed)) == hipSuccess &&
             hipMemset(c->seed_table, 0, SEED_TABLE_CAP * sizeof(DevSeed)) == hipSuccess &&
             hipMalloc(&c->m_dev, 8) == hipSuccess &&
-            hipHostMalloc(&c->counts_host, 257 * 8, hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(&c->counts_host, 258 * 8, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipMemcpy(c->tw_fwd, f.data(), 2 * T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(c->tw_inv, iv.data(), 2 * T * sizeof(uint2), hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(c->g_lo, lo.data(), 4096 * 4, hipMemcpyHostToDevice) == hipSuccess;
@@ -652,10 +672,15 @@ qrng_status qrng_minentropy_subset(qrng_ctx* ctx, const uint8_t* samples, uint64
   CtxScope cs(ctx);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int K = 1 << N;
+  const int fm = fault_mode();
+  if (fm == FAULT_LAUNCH) return fail(QRNG_EDEVICE, "injected launch failure (QRNG_FAULT=launch)");
+  ctx->est_epoch = (ctx->est_epoch + 1) & ((1u << 23) - 1);
   HIP_TRY(hist_estimate(samples, S, N, ctx->hist_scratch, ctx->counts_dev, nullptr, s,
-                        subset_seed, keep_thr));
-  HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 1) * 8, hipMemcpyDeviceToHost, s));
+                        subset_seed, keep_thr, ctx->est_epoch, fm == FAULT_ROWS ? 1u : 0u));
+  HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 2) * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (ctx->counts_host[K + 1] != 1)
+    return fail(QRNG_EDEVICE, "the partial histograms failed their consistency check");
   if (ctx->counts_host[K])
     return fail(QRNG_EINVAL, "%llu samples are >= 2^%d", ctx->counts_host[K], N);
   uint64_t kept = 0;
@@ -908,11 +933,25 @@ qrng_status qrng_extract(qrng_ctx* ctx, const uint8_t* samples, uint64_t S,
   const int hp = path == QRNG_PATH_AUTO ? choose_path(n, m_cap) : path;
   NttPlan pl;
   if (hp == QRNG_PATH_NTT && ntt_make_plan(n, m_cap, &pl) && ntt_fuses_estimate(pl)) {
-    const EstJob job{samples, S, ctx->hist_scratch, a};
+    ctx->est_epoch = (ctx->est_epoch + 1) & ((1u << 23) - 1);
+    const int fm = fault_mode();
+    if (fm == FAULT_TICKET) {
+      // a launch of another call that never completed: its tag, 7 counted
+      const uint32_t stale = ((ctx->est_epoch ^ 0x55u) << 9) | 7u;
+      HIP_TRY(hipMemcpyAsync(ctx->hist_scratch + hist_ticket_word(), &stale, 4,
+                             hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    const EstJob job{samples, S, ctx->hist_scratch, a, ctx->est_epoch,
+                     fm == FAULT_ROWS ? 1u : 0u};
     return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y,
                     hp, s, 1, 0, 0, md, &job);
   }
-  HIP_TRY(hist_estimate(samples, S, 8, ctx->hist_scratch, nullptr, &a, s));
+  if (fault_mode() == FAULT_LAUNCH)
+    return fail(QRNG_EDEVICE, "injected launch failure (QRNG_FAULT=launch)");
+  ctx->est_epoch = (ctx->est_epoch + 1) & ((1u << 23) - 1);
+  HIP_TRY(hist_estimate(samples, S, 8, ctx->hist_scratch, nullptr, &a, s, 0, 0, ctx->est_epoch,
+                        fault_mode() == FAULT_ROWS ? 1u : 0u));
   return hash_one(ctx, reinterpret_cast<const uint64_t*>(samples), n, sd.ptr, &sd, m_cap, y, path,
                   s, 1, 0, 0, md);
 }

@@ -373,7 +373,8 @@ qrng_status qrng_server_feed(qrng_server* s, const uint8_t* samples, void* strea
   a.m_cap = s->cfg.block_bits;
   a.out = s->me + slot;
   a.m_out = s->m_dev + slot;
-  SRV_HIP(hist_estimate(dst, W, 8, s->hist, nullptr, &a, s->est_stream));
+  SRV_HIP(hist_estimate(dst, W, 8, s->hist, nullptr, &a, s->est_stream, 0, 0,
+                        (uint32_t)((s->fed + 1) & ((1u << 23) - 1))));
   SRV_HIP(hipMemcpyAsync(s->m_host + slot, s->m_dev + slot, 8, hipMemcpyDeviceToHost,
                          s->est_stream));
   Window w;
