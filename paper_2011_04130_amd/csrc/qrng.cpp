@@ -21,6 +21,7 @@
 
 #include "qrng.h"
 #include "internal.h"
+#include "host_logic.h"
 
 using namespace qrng;
 
@@ -373,77 +374,6 @@ qrng_status check_modified_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n,
   return QRNG_OK;
 }
 
-double phi(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
-
-constexpr double kTieRel = 1e-9;  // relative closeness treated as a tie of model bins
-
-// Sec. II on the host: model P, H_min, d_U, Delta H_m, H_modify.
-void minentropy_finish(const unsigned long long* c, int N, const qrng_me_opts& o,
-                       qrng_me_result* r) {
-  const int K = 1 << N;
-  double S = 0.0;
-  for (int v = 0; v < K; ++v) S += (double)c[v];
-  double mu, sigma;
-  if (o.model == QRNG_MODEL_GIVEN) {
-    mu = o.mu;
-    sigma = o.sigma;
-  } else {
-    double s1 = 0.0;
-    for (int v = 0; v < K; ++v) s1 += (double)v * (double)c[v];
-    mu = s1 / S;
-    double s2 = 0.0;
-    for (int v = 0; v < K; ++v) s2 += ((double)v - mu) * ((double)v - mu) * (double)c[v];
-    // Sec. II.B: the quantum part of the variance, sigma_q^2 = sigma^2 - sigma_c^2
-    const double var = s2 / S - (o.model == QRNG_MODEL_QUANTUM ? o.sigma * o.sigma : 0.0);
-    sigma = var > 0.0 ? std::sqrt(var) : 0.0;
-  }
-  std::vector<double> P(K);
-  if (sigma > 0.0) {
-    for (int v = 0; v < K; ++v) {
-      const double lo = v == 0 ? 0.0 : phi(((double)v - 0.5 - mu) / sigma);
-      const double hi = v == K - 1 ? 1.0 : phi(((double)v + 0.5 - mu) / sigma);
-      P[v] = hi - lo;
-    }
-  } else {  // every sample equal: the model is a point mass
-    const double at = std::min<double>(std::max<double>(std::floor(mu + 0.5), 0.0), K - 1);
-    for (int v = 0; v < K; ++v) P[v] = (v == (int)at) ? 1.0 : 0.0;
-  }
-  // model argmax: lowest value whose P is within kTieRel of the maximum (a
-  // model centred between two codes has two equal bins; rounding must not
-  // decide between them); observed argmax: lowest value on exact ties
-  double pmax = P[0];
-  int ua = 0;
-  for (int v = 1; v < K; ++v) {
-    pmax = std::max(pmax, P[v]);
-    if (c[v] > c[ua]) ua = v;
-  }
-  int um = 0;
-  while (P[um] < pmax * (1.0 - kTieRel)) ++um;
-  std::vector<int> U;
-  if (o.u_mode == QRNG_U_MODEL_ARGMAX) {
-    U.push_back(um);
-  } else if (o.u_mode == QRNG_U_BOTH_ARGMAX) {
-    // every value tied for the model's maximum, and the observed argmax
-    for (int v = 0; v < K; ++v)
-      if (P[v] >= pmax * (1.0 - kTieRel) || v == ua) U.push_back(v);
-  } else {
-    for (int v = 0; v < K; ++v) U.push_back(v);
-  }
-  double d = 0.0;
-  for (int u : U) d += std::fabs((double)c[u] / S - P[u]);
-  d *= 0.5;
-  r->mu_hat = mu;
-  r->sigma_hat = sigma;
-  r->h_min = -std::log2(pmax);
-  r->h_actual = c[ua] ? -std::log2((double)c[ua] / S) : INFINITY;
-  r->d_u = d;
-  r->delta_h_m = std::log2(d * std::ldexp(1.0, N + 1) + 1.0);
-  r->h_mod = r->h_min - r->delta_h_m;
-  r->argmax_model = (uint32_t)um;
-  r->argmax_empirical = (uint32_t)ua;
-  r->samples = (uint64_t)S;
-}
-
 }  // namespace
 
 namespace qrng {
@@ -641,14 +571,7 @@ qrng_status qrng_output_bits(uint64_t n, int sample_bits, double h_mod, double l
   if (sample_bits < 1 || sample_bits > 16) return fail(QRNG_EINVAL, "sample_bits out of range");
   if (std::isnan(h_mod) || std::isnan(log2_inv_eps) || log2_inv_eps < 0)
     return fail(QRNG_EINVAL, "bad entropy or security parameter");
-  // whole bits per sample, never below 0 nor above the sample width
-  double h = std::floor(h_mod);
-  if (!(h > 0)) h = 0;
-  if (h > sample_bits) h = sample_bits;
-  const uint64_t base = (uint64_t)((unsigned __int128)n * (uint64_t)h / (uint64_t)sample_bits);
-  const double secd = std::ceil(2.0 * log2_inv_eps);
-  const uint64_t sec = secd >= 1.8e19 ? UINT64_MAX : (uint64_t)secd;
-  *m_out = base > sec ? base - sec : 0;
+  *m_out = host::output_bits_rule(n, sample_bits, h_mod, log2_inv_eps);
   return QRNG_OK;
 }
 
@@ -688,7 +611,7 @@ qrng_status qrng_minentropy_subset(qrng_ctx* ctx, const uint8_t* samples, uint64
   if (kept == 0) return fail(QRNG_EINVAL, "the subset keeps no sample");
   if (counts_host)
     for (int v = 0; v < K; ++v) counts_host[v] = ctx->counts_host[v];
-  minentropy_finish(ctx->counts_host, N, *opts, out);
+  host::minentropy_finish(ctx->counts_host, N, *opts, out);
   return QRNG_OK;
 }
 

@@ -16,6 +16,7 @@
 #include <unordered_set>
 #include <vector>
 
+#include "host_logic.h"
 #include "internal.h"
 #include "qrng.h"
 
@@ -43,11 +44,6 @@ struct Admitted {
   hipEvent_t done;  // shared by the requests of one launch run (owned by `events`)
 };
 
-struct Region {
-  uint64_t words;
-  bool released;
-};
-
 }  // namespace
 
 // Hash launches allowed in flight: one running and one queued behind it.
@@ -68,8 +64,7 @@ struct qrng_server {
   uint64_t* m_host = nullptr;                // pinned, per slot
   uint64_t* ring = nullptr;
   uint64_t ring_words = 0;
-  uint64_t head = 0, tail = 0;               // ring words allocated / reclaimed (monotone)
-  std::map<uint64_t, Region> regions;        // by monotone start word
+  host::OutputRing out;                      // allocation of the ring's words
   std::map<uint64_t, uint64_t> region_of;    // request id -> start word
   std::map<uint64_t, uint64_t> served_bits;  // request id -> R, while its space is held
   std::deque<Window> windows;                // fed, oldest first
@@ -104,34 +99,6 @@ hipEvent_t get_event(qrng_server* s) {
   hipEvent_t e = nullptr;
   if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
   return e;
-}
-
-// Output ring: contiguous regions at increasing (monotone) word positions;
-// a region that would cross the end starts at the beginning instead (the
-// skipped tail is a region released at once).  Space comes back in order.
-bool ring_alloc(qrng_server* s, uint64_t words, uint64_t* start) {
-  const uint64_t R = s->ring_words;
-  if (words == 0 || words > R) return false;
-  uint64_t pad = 0;
-  const uint64_t pos = s->head % R;
-  if (pos + words > R) pad = R - pos;
-  if (s->head + pad + words - s->tail > R) return false;
-  if (pad) {
-    s->regions[s->head] = Region{pad, true};
-    s->head += pad;
-  }
-  s->regions[s->head] = Region{words, false};
-  *start = s->head;
-  s->head += words;
-  return true;
-}
-
-void ring_reclaim(qrng_server* s) {
-  while (!s->regions.empty() && s->regions.begin()->second.released) {
-    s->tail = s->regions.begin()->first + s->regions.begin()->second.words;
-    s->regions.erase(s->regions.begin());
-  }
-  if (s->regions.empty()) s->tail = s->head;
 }
 
 // Drop windows that are exhausted and no longer read by pending hashes.
@@ -299,6 +266,7 @@ qrng_status qrng_server_create(qrng_ctx* ctx, const qrng_server_cfg* cfg, qrng_s
     return err(QRNG_ENOMEM, "server buffers");
   }
   s->ring_words = c.ring_bits / 64;
+  s->out.words = s->ring_words;
   s->slot_busy.assign(K, false);
   if (c.block_bits == 0) {
     // serving block length: the candidate that extracts the most bits/s
@@ -419,12 +387,11 @@ qrng_status qrng_server_release_many(qrng_server* s, const uint64_t* ids, uint32
   for (uint32_t i = 0; i < count; ++i) {
     auto it = s->region_of.find(ids[i]);
     if (it == s->region_of.end() || s->inflight_ids.count(ids[i])) continue;
-    auto r = s->regions.find(it->second);
-    if (r != s->regions.end()) r->second.released = true;
+    s->out.release(it->second);
     s->region_of.erase(it);
     s->served_bits.erase(ids[i]);
   }
-  ring_reclaim(s);
+  s->out.reclaim();
   return QRNG_OK;
 }
 
@@ -471,7 +438,7 @@ qrng_status qrng_server_step(qrng_server* s, uint32_t* admitted) {
         break;
       }
       uint64_t start = 0;
-      if (!ring_alloc(s, k * (w.m_s / 64), &start)) {
+      if (!s->out.alloc(k * (w.m_s / 64), &start)) {
         ring_full = true;
         break;
       }
@@ -570,11 +537,10 @@ qrng_status qrng_server_release(qrng_server* s, uint64_t id) {
   auto it = s->region_of.find(id);
   if (it == s->region_of.end()) return err(QRNG_EINVAL, "no ring space held by this request");
   if (s->inflight_ids.count(id)) return err(QRNG_EBUSY, "request not completed yet");
-  auto r = s->regions.find(it->second);
-  if (r != s->regions.end()) r->second.released = true;
+  s->out.release(it->second);
   s->region_of.erase(it);
   s->served_bits.erase(id);
-  ring_reclaim(s);
+  s->out.reclaim();
   return QRNG_OK;
 }
 
@@ -584,8 +550,7 @@ qrng_status qrng_server_read(qrng_server* s, uint64_t id, uint64_t* out, void* s
   auto it = s->region_of.find(id);
   if (it == s->region_of.end()) return err(QRNG_EINVAL, "no ring space held by this request");
   if (s->inflight_ids.count(id)) return err(QRNG_EBUSY, "request not completed yet");
-  auto r = s->regions.find(it->second);
-  if (r == s->regions.end()) return err(QRNG_EINVAL, "request region missing");
+  if (!s->out.find(it->second)) return err(QRNG_EINVAL, "request region missing");
   // the request's bits: R of the words it holds
   const auto sb = s->served_bits.find(id);
   if (sb == s->served_bits.end()) return err(QRNG_EINVAL, "unknown request");
@@ -628,7 +593,7 @@ qrng_status qrng_server_query(qrng_server* s, qrng_server_stats* st) {
   st->bits_served = s->bits_served;
   st->queued = s->queue.size();
   st->in_flight = s->inflight.size();
-  st->ring_free_bits = (s->ring_words - (s->head - s->tail)) * 64;
+  st->ring_free_bits = s->out.free_words() * 64;
   st->m_block = 0;
   for (auto& w : s->windows)
     if (w.known && w.cursor < s->nblk) {
