@@ -286,6 +286,22 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
         torch.cuda.synchronize()
         plan.close()
         got, got_m = y.cpu().numpy(), m_out.cpu().numpy()
+        # the persistent multi-class form (three launches per replay), timed
+        # beside the tuned choice and checked against it
+        table = ctx.tune_export()
+        key = "multi %d " % math.ceil(math.log2(len(ns)))
+        ctx.tune_import(key + "1")
+        y_mc = torch.empty(yo, dtype=torch.int64, device="cuda:0")
+        m_mc = torch.zeros(len(ns), dtype=torch.int64, device="cuda:0")
+        pmc = ctx.plan(rows, x, y_mc, m_out=m_mc, estimate=True, graph=True)
+        t_mc = _time_fn(torch, pmc.execute, reps)
+        mc_launches = pmc.info()["launches"]
+        pmc.close()
+        torch.cuda.synchronize()
+        mc_same = bool(torch.equal(y_mc, y) and torch.equal(m_mc, m_out))
+        prev = [ln for ln in table.splitlines() if ln.startswith(key)]
+        ctx.tune_import(prev[0] if prev else key + "0")
+        del y_mc, m_mc
 
         # the same blocks, one plain single-block call each
         y_p = torch.empty(yo, dtype=torch.int64, device="cuda:0")
@@ -326,7 +342,7 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
                if plain_m[b] != got_m[b] or not np.array_equal(
                    got[rows[b][3]:rows[b][3] + (int(ns[b]) + 63) // 64],
                    plain[rows[b][3]:rows[b][3] + (int(ns[b]) + 63) // 64])]
-        out["verified_vs_plain_calls"] = not bad
+        out["verified_vs_plain_calls"] = not bad and mc_same
         if bad:
             out["mismatched_blocks"] = bad[:16]
 
@@ -344,6 +360,10 @@ def bench_uneven(ctx, q, torch, qi, reps=10):
                                        "graph_replay": round(t_plain_graph * 1e3, 3)},
                     "plain_calls_raw_gbps": round(ns.sum() / t_best_plain / 1e9, 3),
                     "raw_vs_plain": round(t_best_plain / t, 3),
+                    "persistent_multiclass": {"ms_per_step": round(t_mc * 1e3, 4),
+                                              "launches": mc_launches,
+                                              "raw_gbps": round(ns.sum() / t_mc / 1e9, 3),
+                                              "same_bits": mc_same},
                     "classes": info["classes"], "launch_groups": info["launches"],
                     "workspace_MiB": round(info["workspace_bytes"] / 2 ** 20, 1),
                     "kernels_ms": {k: round(ms, 4) for k, (c, ms) in prof.items()},

@@ -44,40 +44,11 @@ __global__ __launch_bounds__(256) void k_hist_finish(HistArgs a) {
   hist_finish_body<256>(a, L);
 }
 
-// One workgroup per block of an uneven batch: histogram of the block's
-// 8-bit samples in LDS sub-histograms, then its estimate and output
-// length.  Sample bytes start 8-byte aligned; S is a
-// multiple of 8.
+// One workgroup per block of an uneven batch (block_estimate_body).
 __global__ __launch_bounds__(256) void k_block_estimate(MeBatchArgs a) {
   __shared__ uint32_t h[HC * HB];
-  const MeBlock blk = a.blocks[blockIdx.x];
-  const int v = threadIdx.x;
-  for (int i = v; i < HC * HB; i += 256) h[i] = 0u;
-  __syncthreads();
-  uint32_t* hw = h + (v % HC) * HB;
-  const uint2* s2 = reinterpret_cast<const uint2*>(a.pool + blk.byte_off);
-  const uint32_t nv = blk.S >> 3;
-  uint32_t i = v;
-  for (; i + 3 * 256 < nv; i += 4 * 256) {
-    uint2 w[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = s2[i + k * 256];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      count_word(hw, w[k].x, 256u);
-      count_word(hw, w[k].y, 256u);
-    }
-  }
-  for (; i < nv; i += 256) {
-    const uint2 w = s2[i];
-    count_word(hw, w.x, 256u);
-    count_word(hw, w.y, 256u);
-  }
-  __syncthreads();
   __shared__ double lds[me_lds_doubles(256)];
-  me_estimate<256>((double)merged<HC>(h, v), 8, a.model, a.u_mode, a.mu,
-              a.sigma, blk.n, a.log2_inv_eps, blk.m_cap, a.out ? a.out + blockIdx.x : nullptr,
-              a.m_out + blockIdx.x, lds);
+  block_estimate_body<256>(a, blockIdx.x, h, lds);
 }
 
 }  // namespace

@@ -228,6 +228,41 @@ __device__ inline uint32_t merged(const uint32_t* h, int b) {
   return t;
 }
 
+// Block b of an uneven batch, run by a workgroup of NT threads: histogram of
+// the block's 8-bit samples in LDS sub-histograms h (HC * HB words), then its
+// estimate and output length (lds: me_lds_doubles(NT) doubles).  Sample
+// bytes start 8-byte aligned; S is a multiple of 8.
+template <int NT>
+__device__ void block_estimate_body(const MeBatchArgs& a, uint32_t b, uint32_t* h, double* lds) {
+  const MeBlock blk = a.blocks[b];
+  const int v = threadIdx.x;
+  for (int i = v; i < HC * HB; i += NT) h[i] = 0u;
+  __syncthreads();
+  uint32_t* hw = h + (v % HC) * HB;
+  const uint2* s2 = reinterpret_cast<const uint2*>(a.pool + blk.byte_off);
+  const uint32_t nv = blk.S >> 3;
+  uint32_t i = v;
+  for (; i + 3 * NT < nv; i += 4 * NT) {
+    uint2 w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = s2[i + k * NT];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      count_word(hw, w[k].x, 256u);
+      count_word(hw, w[k].y, 256u);
+    }
+  }
+  for (; i < nv; i += NT) {
+    const uint2 w = s2[i];
+    count_word(hw, w.x, 256u);
+    count_word(hw, w.y, 256u);
+  }
+  __syncthreads();
+  me_estimate<NT>(v < 256 ? (double)merged<HC>(h, v) : 0.0, 8, a.model, a.u_mode, a.mu, a.sigma,
+                  blk.n, a.log2_inv_eps, blk.m_cap, a.out ? a.out + b : nullptr, a.m_out + b,
+                  lds);
+}
+
 // The estimate on a random subset of the samples (Sec. II.C suggests it as a
 // cheaper route): sample t is kept when the high 32 bits of output t of the
 // SplitMix64 generator seeded with `seed` (Steele, Lea and Flood's

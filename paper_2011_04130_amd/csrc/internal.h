@@ -158,6 +158,42 @@ hipError_t ntt_hash_items_dev(const NttPlan& p, const uint32_t* x_pool, const Nt
                               uint32_t* y_pool, uint32_t* work, const TwTables& tw,
                               hipStream_t s);
 
+// ------------------------------------- persistent multi-class passes (plans)
+// An uneven batch whose blocks span several transform lengths, hashed by
+// three persistent launches (one per four-step pass) instead of three per
+// class.  Classes keep ntt_make_plan's split (rows of 2^10 .. 2^12 points),
+// whose order the cached seed spectra follow.  A launch's workgroups pull
+// work units from an atomic counter: pass A (512 threads): column tiles (32
+// columns of one item); pass B (256 threads): the blocks' estimates (one unit
+// each), then 2 or 4 rows of one item; pass C (512 threads): column tiles.  Classes are stored longest first, so the largest units are handed
+// out first.  Each pass's unit-0 workgroup zeroes the counter of the pass
+// before it (the counters start at 0), so the three launches can be replayed
+// as a graph with no other node.
+constexpr int MC_MAX = 16;
+constexpr int MC_MIN_LOG = 16, MC_MAX_LOG = 21;  // transform lengths these launches cover
+struct MeBatchArgs;
+struct McInfo {
+  uint32_t nclass;
+  uint32_t units[3];  // units of passes A, B, C (B: nest estimate units first)
+  uint32_t nest;
+  uint32_t* counters;  // 3 unit counters (device, zero before the first launch)
+};
+// Bytes of the device argument block for the classes below.
+uint64_t mc_args_bytes();
+// Builds the host image of the argument block (copied to dev_args by the
+// caller): class c has log_nc[c], items[c] items at items_dev[c] and
+// workspace work[c] (items[c] << log_nc[c] words); m_arr: valid lengths by
+// blk (nullable); est (nullable): the per-block estimates of pass B.
+bool mc_build(void* host_image, McInfo* info, int nclass, const int* log_nc,
+              const uint32_t* items, const NttItem* const* items_dev, uint32_t* const* work,
+              const uint32_t* x_pool, uint32_t* y_pool, const uint64_t* m_arr,
+              const MeBatchArgs* est, uint32_t nest, uint32_t* counters);
+// One launch of pass `pass` (0, 1, 2) with `grid` workgroups.
+hipError_t mc_launch(int pass, const void* dev_args, const McInfo& info, uint32_t grid,
+                     const TwTables& tw, hipStream_t s);
+// Workgroups of pass `pass` that fit the device at once.
+uint32_t mc_grid(int pass, int num_cus);
+
 // ------------------------------------------------------------- direct path
 // `batch` blocks sharing one seed: block z reads x_bits + z*x_stride_bits and
 // writes y_bits + z*y_stride_bits (strides multiples of 64).

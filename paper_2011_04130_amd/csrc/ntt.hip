@@ -34,6 +34,8 @@
 // from tables use Shoup products, generated ones Montgomery products.
 #include <utility>
 
+#include <cstring>
+
 #include "common.h"
 #include "hist_dev.h"
 #include "internal.h"
@@ -285,39 +287,26 @@ constexpr int est_copies() {
   return LOG1 >= 9 ? 32 : (LOG1 == 8 ? 16 : 8);
 }
 
-template <int LOG1>
-__global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(ColFwdArgs a,
-                                                                            TwTables tw) {
-  constexpr int NS = cslots<LOG1, false>();
-  __shared__ __align__(16) uint32_t lds[(1 << LOG1) * COLS];
-  __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
-  if (blockIdx.x < a.hg) {
-    if constexpr (LOG1 >= 7) {
-      static_assert(est_copies<LOG1>() * hd::HB <= (1 << LOG1) * COLS &&
-                        sizeof(hd::FinishLds) <= sizeof(lds),
-                    "estimate workgroup fits the column LDS");
-      if (blockIdx.y == 0)
-        hd::estimate_workgroup<COLS * NS, est_copies<LOG1>()>(a.est, blockIdx.x, a.ticket,
-                                                                  lds);
-    }
-    return;
-  }
-  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
-  const int bx = blockIdx.x - a.hg;  // column block
+// Pass A on column block bx of item `item` (NS slots of 32 threads; lds:
+// (1 << LOG1) * COLS words, wbits: 1 << LOG1 words).
+template <int LOG1, int NS>
+__device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTables& tw, int bx,
+                                              int item, uint32_t* __restrict__ lds,
+                                              uint32_t* __restrict__ wbits) {
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int32_t Nc = 1 << a.log_nc;
   const int j2 = bx * COLS + c;
   const uint32_t* __restrict__ bits;
   BitMap mp;
   if (a.items) {
-    const NttItem& it = a.items[blockIdx.y];
+    const NttItem& it = a.items[item];
     bits = a.bits + (it.x_bit >> 5);
     mp = rotated_block(it.n, Nc);
   } else {
-    bits = a.bits + (uint64_t)(blockIdx.y / a.nmap) * (a.zs >> 5);
-    mp = a.map[blockIdx.y % a.nmap];
+    bits = a.bits + (uint64_t)(item / a.nmap) * (a.zs >> 5);
+    mp = a.map[item % a.nmap];
   }
-  uint32_t* __restrict__ out = a.out + (uint64_t)blockIdx.y * (uint32_t)Nc;
+  uint32_t* __restrict__ out = a.out + (uint64_t)item * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   const int l2 = a.log2;
 
@@ -369,6 +358,27 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(Col
   });
 }
 
+template <int LOG1>
+__global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(ColFwdArgs a,
+                                                                            TwTables tw) {
+  constexpr int NS = cslots<LOG1, false>();
+  __shared__ __align__(16) uint32_t lds[(1 << LOG1) * COLS];
+  __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
+  if (blockIdx.x < a.hg) {
+    if constexpr (LOG1 >= 7) {
+      static_assert(est_copies<LOG1>() * hd::HB <= (1 << LOG1) * COLS &&
+                        sizeof(hd::FinishLds) <= sizeof(lds),
+                    "estimate workgroup fits the column LDS");
+      if (blockIdx.y == 0)
+        hd::estimate_workgroup<COLS * NS, est_copies<LOG1>()>(a.est, blockIdx.x, a.ticket,
+                                                                  lds);
+    }
+    return;
+  }
+  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
+  cols_fwd_body<LOG1, NS>(a, tw, blockIdx.x - a.hg, blockIdx.y, lds, wbits);
+}
+
 // ----------------------------------------------------------------- pass C
 struct ColInvArgs {
   const uint32_t* in;  // item y = blockIdx.y at in + y * Nc
@@ -391,26 +401,25 @@ __device__ __forceinline__ uint64_t valid_bits(uint64_t m, const uint64_t* m_dev
   return d < m ? d : m;
 }
 
-template <int LOG1>
-__global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColInvArgs a,
-                                                                           TwTables tw) {
-  constexpr int NS = cslots<LOG1, true>();
-  __shared__ uint32_t lds[(1 << LOG1) * COLS];
-  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
+// Pass C on column block bx of item `item` (NS slots of 32 threads; lds:
+// (1 << LOG1) * COLS words).
+template <int LOG1, int NS>
+__device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTables& tw, int bx,
+                                              int item, uint32_t* __restrict__ lds) {
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
   const int lane = threadIdx.x & 63;
   const int32_t Nc = 1 << a.log_nc;
-  const int j2 = blockIdx.x * COLS + c;
-  const int o = blockIdx.y % a.ny;
+  const int j2 = bx * COLS + c;
+  const int o = item % a.ny;
   uint64_t ybase, m;
   const uint64_t* m_dev;
   if (a.items) {
-    const NttItem& it = a.items[blockIdx.y];
+    const NttItem& it = a.items[item];
     ybase = it.y_bit;
     m = it.m;
     m_dev = a.m_arr ? a.m_arr + it.blk : nullptr;
   } else {
-    ybase = (uint64_t)(blockIdx.y / a.ny) * a.y_zs + (uint64_t)o * a.by;
+    ybase = (uint64_t)(item / a.ny) * a.y_zs + (uint64_t)o * a.by;
     m = a.m;
     m_dev = a.m_dev;
   }
@@ -419,7 +428,7 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColI
   const int64_t rem = (int64_t)valid_bits(m, m_dev) - (int64_t)o * a.by;
   const int32_t yvalid = (int32_t)(rem < a.by ? (rem < 0 ? 0 : rem) : a.by);
   uint32_t* __restrict__ ywords = a.y + (ybase >> 5);
-  const uint32_t* __restrict__ in = a.in + (uint64_t)blockIdx.y * (uint32_t)Nc;
+  const uint32_t* __restrict__ in = a.in + (uint64_t)item * (uint32_t)Nc;
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   constexpr uint32_t EMASK = (1u << LOG_MAX) - 1;
   const int l2 = a.log2;
@@ -473,6 +482,15 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColI
   });
 }
 
+template <int LOG1>
+__global__ __launch_bounds__((COLS * cslots<LOG1, true>())) void k_cols_inv(ColInvArgs a,
+                                                                           TwTables tw) {
+  constexpr int NS = cslots<LOG1, true>();
+  __shared__ uint32_t lds[(1 << LOG1) * COLS];
+  if (a.count && a.item0 + blockIdx.y >= *a.count) return;
+  cols_inv_body<LOG1, NS>(a, tw, blockIdx.x, blockIdx.y, lds);
+}
+
 // ----------------------------------------------------------------- pass B
 struct RowArgs {
   const uint32_t* in;  // residues (pass-A output); item at in + item * Nc + row * N2
@@ -507,22 +525,34 @@ constexpr int row_threads() {
 // writes hash bits directly.  The last forward round and the first inverse
 // round act on the same 16 contiguous positions per group, so the seed
 // product happens in registers between them.
+// LDS words of one row buffer (one pad word per 16)
+template <int LOG2>
+constexpr int row_lds_words() {
+  return (1 << LOG2) + (1 << LOG2) / 16;
+}
+// Two raw chunks of a hash are transformed side by side, one LDS buffer
+// each, so every round of both rows shares one barrier (and, with two
+// output chunks, so are the two inverse transforms).
+template <int NX, bool IN_BITS, bool SEED, bool OUT_BITS>
+constexpr bool rows_joint() {
+  return NX == 2 && !SEED && !IN_BITS && !OUT_BITS;
+}
+
+// Row `row` of item zy, run by threads tid < row_threads<LOG2, GPT>() of
+// the workgroup (every thread of the workgroup takes part in its barriers);
+// lds: (JOINT ? 2 : 1) * row_lds_words<LOG2>() words; wbits (IN_BITS only):
+// N2 / 32 words.
 template <int LOG2, int NX, int GPT, bool IN_BITS, bool SEED, bool OUT_BITS>
-__global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, TwTables tw) {
+__device__ __forceinline__ void rows_body(const RowArgs& a, const TwTables& tw, int tid, int row,
+                                          int zy, uint32_t* __restrict__ ldsbase,
+                                          uint32_t* __restrict__ wbits) {
   constexpr int N2 = 1 << LOG2, T = row_threads<LOG2, GPT>(), K = RP<LOG2>::K;
   static_assert(K >= 2, "rows are at least 2^5 long");
   static_assert(Geo<LOG2, K - 1>::r == 16 && Geo<LOG2, K - 1>::s == 1, "last round");
-  // Two raw chunks of a hash are transformed side by side, one LDS buffer
-  // each, so every round of both rows shares one barrier (and, with two
-  // output chunks, so are the two inverse transforms).
-  constexpr bool JOINT = NX == 2 && !SEED && !IN_BITS && !OUT_BITS;
-  __shared__ uint32_t ldsb[JOINT ? 2 : 1][N2 + N2 / 16];
+  constexpr bool JOINT = rows_joint<NX, IN_BITS, SEED, OUT_BITS>();
+  uint32_t* const ldsb[2] = {ldsbase, ldsbase + row_lds_words<LOG2>()};
   uint32_t* const lds = ldsb[0];
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int row = blockIdx.x;
-  const int zy = blockIdx.y;
-  if (!SEED && a.count && a.item0 + zy >= *a.count) return;
   const int32_t Nc = 1 << a.log_nc;
   const NttItem* desc = SEED ? nullptr : (a.items ? a.items + zy : nullptr);
   // transposed twiddle tables (lane-contiguous loads) pay off up to 2^13-point
@@ -584,7 +614,6 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
     const int item = SEED ? zy : zy * NX + c;
     if constexpr (IN_BITS) {
       // the whole transform's input bits, 32 positions per LDS word
-      __shared__ uint32_t wbits[N2 / 32];
       const BitMap mp = desc ? rotated_block(desc->n, Nc) : a.map[SEED ? zy : c];
       const uint32_t* __restrict__ bits =
           a.bits + (desc ? (desc->x_bit >> 5) : (SEED ? 0 : (uint64_t)zy * (a.zs >> 5)));
@@ -801,6 +830,16 @@ __global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, 
   }
 }
 
+template <int LOG2, int NX, int GPT, bool IN_BITS, bool SEED, bool OUT_BITS>
+__global__ __launch_bounds__((row_threads<LOG2, GPT>())) void k_rows(RowArgs a, TwTables tw) {
+  constexpr bool JOINT = rows_joint<NX, IN_BITS, SEED, OUT_BITS>();
+  __shared__ uint32_t ldsb[(JOINT ? 2 : 1) * row_lds_words<LOG2>()];
+  __shared__ uint32_t wbits[IN_BITS ? (1 << LOG2) / 32 : 1];
+  if (!SEED && a.count && a.item0 + blockIdx.y >= *a.count) return;
+  rows_body<LOG2, NX, GPT, IN_BITS, SEED, OUT_BITS>(a, tw, threadIdx.x, blockIdx.x, blockIdx.y,
+                                                   ldsb, wbits);
+}
+
 // Two raw and two output chunks: windows (W0, W1, W2) -> (W1, W0 - W1,
 // W2 - W1), the order the three-product row pass reads (values in [0, p)).
 __global__ __launch_bounds__(256) void k_combine3(uint32_t* __restrict__ W, uint32_t Nc) {
@@ -810,6 +849,161 @@ __global__ __launch_bounds__(256) void k_combine3(uint32_t* __restrict__ W, uint
   W[i] = b;
   W[Nc + i] = a >= b ? a - b : a + P - b;
   W[2 * (uint64_t)Nc + i] = c >= b ? c - b : c + P - b;
+}
+
+// ------------------------------------------ persistent multi-class passes
+struct McClassDev {
+  int log_nc, log1, log2, rpu;  // rpu: rows per pass-B unit
+  uint32_t items;
+  uint32_t u0[3];   // first unit of the class in passes A, B, C
+  uint32_t per[3];  // units per item in passes A, B, C
+  ColFwdArgs fa;
+  RowArgs rb;
+  ColInvArgs ic;
+};
+struct McDev {
+  uint32_t nclass, nest;
+  uint32_t units[3];
+  uint32_t* counters;
+  MeBatchArgs est;
+  McClassDev cls[MC_MAX];
+};
+
+// Classes keep the split of ntt_make_plan (rows of 2^10 .. 2^12 points for
+// these lengths, columns of 2^6 .. 2^9), which the cached seed spectra's
+// order follows.
+constexpr int MC_NS = 16;  // slots of 32 columns: 512 threads
+constexpr int MC_T_COLS = COLS * MC_NS;
+constexpr int MC_T_ROWS = 256;  // 2 rows of 2^12 points, or 4 shorter rows
+constexpr int MC_MIN_LOG1 = MC_MIN_LOG - 10, MC_MAX_LOG1 = 9;  // column lengths
+
+// Next unit of pass P for this workgroup (all threads get it); the taker of
+// unit 0 clears the counter of the pass before (pass P-1 mod 3), which has
+// completed: the launches run in stream order.
+template <int P>
+__device__ __forceinline__ uint32_t mc_next(const McDev* __restrict__ d, uint32_t* slot) {
+  if (threadIdx.x == 0) {
+    const uint32_t u = atomicAdd(&d->counters[P], 1u);
+    if (u == 0) atomicExch(&d->counters[(P + 2) % 3], 0u);
+    *slot = u;
+  }
+  __syncthreads();
+  // the same value in every lane: keep it (and all that follows from it,
+  // the class and its arguments) in scalar registers
+  const uint32_t u = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();
+  return u;
+}
+
+// the class of unit u of pass P (classes are in unit order)
+template <int P>
+__device__ __forceinline__ int mc_class(const McDev* __restrict__ d, uint32_t u) {
+  int c = 0;
+  while (c + 1 < (int)d->nclass && u >= d->cls[c + 1].u0[P]) ++c;
+  return c;
+}
+
+// The tables as seen by one unit: the empty asm makes each pointer look
+// rewritten, so the compiler cannot hoist a unit's table loads out of the
+// unit loop (they would stay live, in registers, across all units).
+__device__ __forceinline__ TwTables fresh_tables(const TwTables& tw) {
+  TwTables t = tw;
+  asm volatile("" : "+s"(t.fwd), "+s"(t.inv), "+s"(t.fwd_t), "+s"(t.inv_t), "+s"(t.g_lo),
+               "+s"(t.g_hi));
+  return t;
+}
+
+template <int L, int E, class F>
+__device__ __forceinline__ void static_switch(int v, F&& f) {
+  if constexpr (L <= E) {
+    if (v == L)
+      f(std::integral_constant<int, L>{});
+    else
+      static_switch<L + 1, E>(v, f);
+  }
+}
+
+__global__ __launch_bounds__(MC_T_COLS, 4) void k_mc_cols_fwd(const McDev* __restrict__ d,
+                                                          TwTables tw) {
+  __shared__ __align__(16) uint32_t lds[(1 << MC_MAX_LOG1) * COLS];
+  __shared__ uint32_t wbits[1 << MC_MAX_LOG1];
+  __shared__ uint32_t slot;
+  for (;;) {
+    const uint32_t u = mc_next<0>(d, &slot);
+    if (u >= d->units[0]) return;
+    const McClassDev& C = d->cls[mc_class<0>(d, u)];
+    const uint32_t local = u - C.u0[0];
+    const int item = (int)(local / C.per[0]), tile = (int)(local % C.per[0]);
+    const TwTables t = fresh_tables(tw);
+    static_switch<MC_MIN_LOG1, MC_MAX_LOG1>(C.log1, [&](auto l) {
+      cols_fwd_body<decltype(l)::value, MC_NS>(C.fa, t, tile, item, lds, wbits);
+    });
+  }
+}
+
+// The estimate unit as a call of its own: inlined, its double-precision
+// code and the row transform would share one register allocation.
+__device__ __noinline__ void mc_estimate_unit(const MeBatchArgs* a, uint32_t b, uint32_t* lds) {
+  hd::block_estimate_body<MC_T_ROWS>(*a, b, lds,
+                                     reinterpret_cast<double*>(lds + ((hd::HC * hd::HB + 1) & ~1)));
+}
+
+__global__ __launch_bounds__(MC_T_ROWS) void k_mc_rows(const McDev* __restrict__ d,
+                                                      TwTables tw) {
+  // MC_T_ROWS / row_threads rows of one item per unit, one per thread group
+  constexpr int RW = (row_lds_words<12>() + 1) & ~1;  // 8-byte aligned
+  static_assert(2 * row_threads<12, 2>() == MC_T_ROWS && 4 * row_threads<11, 2>() == MC_T_ROWS &&
+                    4 * row_threads<10, 1>() == MC_T_ROWS && 4 * row_lds_words<11>() <= 2 * RW,
+                "rows per workgroup");
+  constexpr int EW = ((hd::HC * hd::HB + 1) & ~1) + 2 * hd::me_lds_doubles(MC_T_ROWS);
+  __shared__ __align__(16) uint32_t lds[2 * RW > EW ? 2 * RW : EW];
+  __shared__ uint32_t slot;
+  for (;;) {
+    const uint32_t u = mc_next<1>(d, &slot);
+    if (u >= d->units[1]) return;
+    if (u < d->nest) {
+      mc_estimate_unit(&d->est, u, lds);  // block u's estimate: the m pass C reads
+      continue;
+    }
+    const McClassDev& C = d->cls[mc_class<1>(d, u)];
+    const uint32_t local = u - C.u0[1];
+    const int item = (int)(local / C.per[1]);
+    const int row0 = (int)(local % C.per[1]) * C.rpu;
+    const TwTables t = fresh_tables(tw);
+    if (C.log2 == 12) {
+      constexpr int RT = row_threads<12, 2>();
+      const int g = threadIdx.x / RT;
+      rows_body<12, 1, 2, false, false, false>(C.rb, t, threadIdx.x - g * RT, row0 + g, item,
+                                               lds + g * RW, nullptr);
+    } else if (C.log2 == 11) {
+      constexpr int RT = row_threads<11, 2>();
+      const int g = threadIdx.x / RT;
+      rows_body<11, 1, 2, false, false, false>(C.rb, t, threadIdx.x - g * RT, row0 + g, item,
+                                               lds + g * row_lds_words<11>(), nullptr);
+    } else {
+      constexpr int RT = row_threads<10, 1>();
+      const int g = threadIdx.x / RT;
+      rows_body<10, 1, 1, false, false, false>(C.rb, t, threadIdx.x - g * RT, row0 + g, item,
+                                               lds + g * row_lds_words<10>(), nullptr);
+    }
+  }
+}
+
+__global__ __launch_bounds__(MC_T_COLS, 4) void k_mc_cols_inv(const McDev* __restrict__ d,
+                                                          TwTables tw) {
+  __shared__ uint32_t lds[(1 << MC_MAX_LOG1) * COLS];
+  __shared__ uint32_t slot;
+  for (;;) {
+    const uint32_t u = mc_next<2>(d, &slot);
+    if (u >= d->units[2]) return;
+    const McClassDev& C = d->cls[mc_class<2>(d, u)];
+    const uint32_t local = u - C.u0[2];
+    const int item = (int)(local / C.per[2]), tile = (int)(local % C.per[2]);
+    const TwTables t = fresh_tables(tw);
+    static_switch<MC_MIN_LOG1, MC_MAX_LOG1>(C.log1, [&](auto l) {
+      cols_inv_body<decltype(l)::value, MC_NS>(C.ic, t, tile, item, lds);
+    });
+  }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -976,6 +1170,7 @@ bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* p) {
     p->log1 = 0;
     p->log2 = k;
   } else {
+    // columns of 2^6 .. 2^9 points; rows of 2^10 up to 2^19, longer above
     int l2 = k - 9;
     l2 = l2 < 10 ? 10 : (l2 > MAX_LOG_ROW ? MAX_LOG_ROW : l2);
     p->log2 = l2;
@@ -1208,6 +1403,106 @@ hipError_t ntt_hash_items_dev(const NttPlan& p, const uint32_t* x_pool, const Nt
   ci.count = count;
   ci.item0 = item0;
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, grid_items), tw, s);
+}
+
+uint64_t mc_args_bytes() { return sizeof(McDev); }
+
+bool mc_build(void* host_image, McInfo* info, int nclass, const int* log_nc,
+              const uint32_t* items, const NttItem* const* items_dev, uint32_t* const* work,
+              const uint32_t* x_pool, uint32_t* y_pool, const uint64_t* m_arr,
+              const MeBatchArgs* est, uint32_t nest, uint32_t* counters) {
+  if (nclass < 0 || nclass > MC_MAX) return false;
+  McDev* d = static_cast<McDev*>(host_image);
+  std::memset(d, 0, sizeof(McDev));
+  d->nclass = (uint32_t)nclass;
+  d->nest = est ? nest : 0;
+  if (est) d->est = *est;
+  d->counters = counters;
+  uint64_t u[3] = {0, d->nest, 0};
+  for (int c = 0; c < nclass; ++c) {
+    const int k = log_nc[c];
+    if (k < MC_MIN_LOG || k > MC_MAX_LOG || (c && k > log_nc[c - 1])) return false;
+    McClassDev& C = d->cls[c];
+    NttPlan np;
+    if (!ntt_plan_for_length(k, &np) || np.log1 < MC_MIN_LOG1 || np.log1 > MC_MAX_LOG1 || np.log2 < 10 ||
+        np.log2 > 12)
+      return false;
+    const int l2 = np.log2;  // the split the cached seed spectra are laid out for
+    C.log_nc = k;
+    C.log2 = l2;
+    C.log1 = k - l2;
+    C.rpu = l2 == 12 ? 2 : 4;
+    C.items = items[c];
+    C.per[0] = C.per[2] = (1u << l2) / COLS;
+    C.per[1] = (1u << C.log1) / C.rpu;
+    for (int p = 0; p < 3; ++p) {
+      C.u0[p] = (uint32_t)u[p];
+      u[p] += (uint64_t)C.items * C.per[p];
+    }
+    C.fa.bits = x_pool;
+    C.fa.nmap = 1;
+    C.fa.log2 = l2;
+    C.fa.log_nc = k;
+    C.fa.out = work[c];
+    C.fa.items = items_dev[c];
+    C.rb.nx = C.rb.ny = 1;
+    C.rb.log_nc = k;
+    C.rb.in = work[c];
+    C.rb.out = work[c];
+    C.rb.items = items_dev[c];
+    C.rb.bits = x_pool;
+    C.rb.y = y_pool;
+    C.rb.m_arr = m_arr;
+    C.ic.in = work[c];
+    C.ic.ny = 1;
+    C.ic.log2 = l2;
+    C.ic.log_nc = k;
+    C.ic.y = y_pool;
+    C.ic.by = (int64_t)1 << k;
+    C.ic.items = items_dev[c];
+    C.ic.m_arr = m_arr;
+  }
+  for (int p = 0; p < 3; ++p) {
+    if (u[p] >= (1ull << 32)) return false;
+    d->units[p] = (uint32_t)u[p];
+  }
+  info->nclass = (uint32_t)nclass;
+  for (int p = 0; p < 3; ++p) info->units[p] = d->units[p];
+  info->nest = d->nest;
+  info->counters = counters;
+  return true;
+}
+
+uint32_t mc_grid(int pass, int num_cus) {
+  int per = 0;
+  const void* f = pass == 0 ? (const void*)k_mc_cols_fwd
+                            : (pass == 1 ? (const void*)k_mc_rows : (const void*)k_mc_cols_inv);
+  const int threads = pass == 1 ? MC_T_ROWS : MC_T_COLS;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, 0) != hipSuccess || per < 1)
+    per = 1;
+  return (uint32_t)per * (uint32_t)num_cus;
+}
+
+hipError_t mc_launch(int pass, const void* dev_args, const McInfo& info, uint32_t grid,
+                     const TwTables& tw, hipStream_t s) {
+  const uint32_t units = info.units[pass];
+  if (units == 0) return hipSuccess;
+  const uint32_t g = grid < units ? grid : units;
+  const McDev* d = static_cast<const McDev*>(dev_args);
+  if (pass == 0) {
+    prof_begin(KID_COLS_FWD, s);
+    hipLaunchKernelGGL(k_mc_cols_fwd, dim3(g), dim3(MC_T_COLS), 0, s, d, tw);
+    prof_end(KID_COLS_FWD, s);
+  } else if (pass == 1) {
+    prof_begin(KID_ROWS_HASH, s);
+    hipLaunchKernelGGL(k_mc_rows, dim3(g), dim3(MC_T_ROWS), 0, s, d, tw);
+    prof_end(KID_ROWS_HASH, s);
+  } else {
+    prof_begin(KID_COLS_INV, s);
+    hipLaunchKernelGGL(k_mc_cols_inv, dim3(g), dim3(MC_T_COLS), 0, s, d, tw);
+    prof_end(KID_COLS_INV, s);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace qrng

@@ -1088,6 +1088,11 @@ struct qrng_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint32_t nblocks = 0, classes = 0;
+  // persistent multi-class passes: argument block, unit counters, workspace
+  void* mc_args = nullptr;
+  uint32_t* mc_counters = nullptr;
+  uint32_t* mc_work = nullptr;
+  bool multi = false;
 };
 
 namespace {
@@ -1216,6 +1221,9 @@ void plan_free(qrng_plan* pl) {
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->desc) (void)hipFree(pl->desc);
   if (pl->work) (void)hipFree(pl->work);
+  if (pl->mc_args) (void)hipFree(pl->mc_args);
+  if (pl->mc_counters) (void)hipFree(pl->mc_counters);
+  if (pl->mc_work) (void)hipFree(pl->mc_work);
   for (uint32_t id : pl->seed_ids) {
     auto it = pl->ctx->seeds.find(id);
     if (it != pl->ctx->seeds.end() && it->second.plans) --it->second.plans;
@@ -1352,8 +1360,9 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
 
   // step 1: the per-block estimates
   std::vector<std::function<hipError_t(hipStream_t)>> head;
+  MeBatchArgs est_args{};
   if (estimate) {
-    MeBatchArgs a{};
+    MeBatchArgs& a = est_args;
     a.pool = reinterpret_cast<const uint8_t*>(x_pool);
     a.blocks = reinterpret_cast<const MeBlock*>((char*)pl->desc + ib);
     a.model = opts->model;
@@ -1415,13 +1424,58 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
       ctx->tune[{c.log_nc, tune_key_count(c.ids.size())}] = best_c;
     }
   }
-  uint64_t work_need = 0;
+  // items of the persistent multi-class launches by transform length: the
+  // classes of 2^16 .. 2^21 points, and shorter classes raised to 2^16 points
+  // when every seed they use has that spectrum (any length >= n+m-1 gives
+  // the same bits)
+  std::map<int, std::vector<NttItem>, std::greater<int>> mc_items;
+  std::vector<bool> in_mc(b.classes.size(), false);
+  if (path == QRNG_PATH_AUTO || path == QRNG_PATH_NTT) {
+    for (size_t k = 0; k < b.classes.size(); ++k) {
+      const ClassInfo& c = b.classes[k];
+      if (c.log_nc > MC_MAX_LOG) continue;
+      if (c.log_nc >= MC_MIN_LOG) {
+        auto& v = mc_items[c.log_nc];
+        v.insert(v.end(), items.begin() + (long)c.item_off,
+                 items.begin() + (long)(c.item_off + c.ids.size()));
+        in_mc[k] = true;
+        continue;
+      }
+      std::vector<NttItem> up;
+      for (uint32_t id : c.ids) {
+        const auto& sp = ctx->seeds[blocks[id].seed_id].spectra;
+        auto f = sp.find({0, 1ull << MC_MIN_LOG});
+        if (f == sp.end()) break;
+        const qrng_block& bl = blocks[id];
+        up.push_back(NttItem{bl.x_word_off * 64, bl.y_word_off * 64, f->second, (uint32_t)bl.n,
+                             (uint32_t)bl.m, id, 0});
+      }
+      if (up.size() == c.ids.size()) {
+        auto& v = mc_items[MC_MIN_LOG];
+        v.insert(v.end(), up.begin(), up.end());
+        in_mc[k] = true;
+      }
+    }
+  }
+  if (mc_items.size() > (size_t)MC_MAX) {
+    mc_items.clear();
+    in_mc.assign(b.classes.size(), false);
+  }
+
+  uint64_t work_need = 0, work_other = 0;  // all per-class steps / those outside mc
   pl->steps = head;
+  std::vector<std::function<hipError_t(hipStream_t)>> other;  // classes outside mc
   for (size_t k = 0; k < b.classes.size(); ++k) {
     uint64_t need = 0;
     class_steps(b, b.classes[k], choice[k], slot, &pl->steps, &need);
     work_need = std::max(work_need, need);
+    if (!in_mc[k]) {
+      class_steps(b, b.classes[k], choice[k], slot, &other, &need);
+      work_other = std::max(work_other, need);
+    }
   }
+  std::vector<std::function<hipError_t(hipStream_t)>> singles_steps;
+  const size_t singles_at = pl->steps.size();
   // blocks that need the split transform (or a forced path): one launch each
   for (size_t k = 0; k < b.singles.size(); ++k) {
     const uint32_t id = b.singles[k];
@@ -1456,6 +1510,103 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
       });
     }
   }
+  work_other = std::max(work_other, [&] {
+    // the singles' share of work_need
+    uint64_t w = 0;
+    for (size_t k = 0; k < b.singles.size(); ++k) {
+      const qrng_block bl = blocks[b.singles[k]];
+      NttPlan np;
+      if (b.single_path[k] == QRNG_PATH_NTT && ntt_make_plan(bl.n, bl.m, &np))
+        w = std::max<uint64_t>(w, ntt_work_elems(np, 1) * 4);
+      else if (b.single_path[k] == QRNG_PATH_DIRECT)
+        w = std::max<uint64_t>(w, direct_work_words(bl.n, 1) * 4);
+    }
+    return w;
+  }());
+  singles_steps.assign(pl->steps.begin() + (long)singles_at, pl->steps.end());
+
+  // the persistent multi-class form: three launches for every class in mc
+  // (with the per-block estimates inside the second), then the other classes
+  // and the singles; used when the tuning table or tuning picks it
+  if (!mc_items.empty()) {
+    uint64_t words = 0, nit = 0;
+    for (auto& kv : mc_items) {
+      words += (uint64_t)kv.second.size() << kv.first;
+      nit += kv.second.size();
+    }
+    if (hipMalloc(&pl->mc_work, words * 4) != hipSuccess)
+      return bail(fail(QRNG_ENOMEM, "multi-class workspace of %llu bytes",
+                       (unsigned long long)(words * 4)));
+    if (hipMalloc(&pl->mc_args, mc_args_bytes() + nit * sizeof(NttItem)) != hipSuccess ||
+        hipMalloc(&pl->mc_counters, 16) != hipSuccess ||
+        hipMemset(pl->mc_counters, 0, 16) != hipSuccess)
+      return bail(fail(QRNG_ENOMEM, "multi-class arguments"));
+    NttItem* mc_dev_items =
+        reinterpret_cast<NttItem*>(static_cast<char*>(pl->mc_args) + mc_args_bytes());
+    std::vector<int> lg;
+    std::vector<uint32_t> cnt;
+    std::vector<const NttItem*> idev;
+    std::vector<uint32_t*> wk;
+    std::vector<NttItem> all;
+    uint64_t off = 0;
+    for (auto& kv : mc_items) {
+      lg.push_back(kv.first);
+      cnt.push_back((uint32_t)kv.second.size());
+      idev.push_back(mc_dev_items + all.size());
+      wk.push_back(pl->mc_work + off);
+      off += (uint64_t)kv.second.size() << kv.first;
+      all.insert(all.end(), kv.second.begin(), kv.second.end());
+    }
+    std::vector<char> img(mc_args_bytes());
+    McInfo info{};
+    if (!mc_build(img.data(), &info, (int)lg.size(), lg.data(), cnt.data(), idev.data(),
+                  wk.data(), reinterpret_cast<const uint32_t*>(x_pool),
+                  reinterpret_cast<uint32_t*>(y_pool), b.m_arr, estimate ? &est_args : nullptr,
+                  nblocks, pl->mc_counters))
+      return bail(fail(QRNG_EUNSUPPORTED, "multi-class layout"));
+    if (hipMemcpy(pl->mc_args, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mc_dev_items, all.data(), all.size() * sizeof(NttItem),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(QRNG_EDEVICE, "multi-class arguments upload"));
+    std::vector<std::function<hipError_t(hipStream_t)>> multi;
+    const void* margs = pl->mc_args;
+    const TwTables tw = ctx->tw;
+    for (int pass = 0; pass < 3; ++pass) {
+      const uint32_t grid = mc_grid(pass, ctx->num_cus);
+      multi.push_back([=](hipStream_t st) { return mc_launch(pass, margs, info, grid, tw, st); });
+    }
+    // the estimates run in pass B, so the other classes and the singles,
+    // which read m, come after the three launches
+    multi.insert(multi.end(), other.begin(), other.end());
+    multi.insert(multi.end(), singles_steps.begin(), singles_steps.end());
+    // default: per-class launches (measured faster on the 4096-block
+    // workload: the single persistent kernel of each pass carries the
+    // registers and LDS of its longest class into every unit)
+    const std::pair<int, int> key{0, tune_key_count(nblocks)};
+    bool use_multi = false;
+    auto t = ctx->tune.find(key);
+    if (t != ctx->tune.end()) use_multi = t->second != 0;
+    if (flags & QRNG_PLAN_TUNE) {
+      qrng_status e = plan_alloc_work(pl, std::max<uint64_t>(work_need, 256));
+      if (e) return bail(e);
+      float t_each = 0, t_multi = 0;
+      e = time_steps(pl->steps, s, &t_each);
+      if (!e) e = time_steps(multi, s, &t_multi);
+      if (e) return bail(e);
+      use_multi = t_multi <= t_each;
+      ctx->tune[key] = use_multi ? 1 : 0;
+    }
+    if (use_multi) {
+      pl->steps = multi;
+      pl->multi = true;
+      work_need = work_other;
+    } else {
+      HIP_TRY(hipStreamSynchronize(s));
+      (void)hipFree(pl->mc_work);
+      pl->mc_work = nullptr;
+    }
+  }
+
   // the workspace now fits the chosen shapes (tuning may have left it larger)
   if (pl->work_bytes > 2 * work_need + (64u << 20)) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -1524,8 +1675,12 @@ void qrng_plan_destroy(qrng_plan* pl) {
 qrng_status qrng_tune_export(qrng_ctx* ctx, char* buf, uint64_t cap, uint64_t* len) {
   if (!ctx || !len) return fail(QRNG_EINVAL, "null argument");
   std::ostringstream os;
-  for (auto& kv : ctx->tune)
-    os << "ntt " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+  for (auto& kv : ctx->tune) {
+    if (kv.first.first == 0)  // persistent multi-class form (1) or per-class launches (0)
+      os << "multi " << kv.first.second << " " << kv.second << "\n";
+    else
+      os << "ntt " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+  }
   const std::string t = os.str();
   *len = t.size();
   if (buf) {
@@ -1548,7 +1703,13 @@ qrng_status qrng_tune_import(qrng_ctx* ctx, const char* text) {
     std::istringstream ls(line);
     std::string tag;
     int a = 0, c = 0, v = 0;
-    if (!(ls >> tag >> a >> c >> v) || tag != "ntt" || a < 10 || a > 23 || c < 0 || c > 32 ||
+    if (ls >> tag && tag == "multi") {
+      if (!(ls >> c >> v) || c < 0 || c > 32 || (v != 0 && v != 1))
+        return fail(QRNG_EINVAL, "tuning table line %d is malformed", ln);
+      add[{0, c}] = v;
+      continue;
+    }
+    if (tag != "ntt" || !(ls >> a >> c >> v) || a < 10 || a > 23 || c < 0 || c > 32 ||
         !(v == kTuneDirect || (v >= 10 && v <= kTuneNoCap)))
       return fail(QRNG_EINVAL, "tuning table line %d is malformed", ln);
     add[{a, c}] = v;

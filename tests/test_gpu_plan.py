@@ -185,7 +185,7 @@ def test_plan_tune_table_roundtrip(torch, ctx):
             check_blocks(rows, xw, {sid: sw}, host(y))
         table = ctx.tune_export()
         lines = [ln for ln in table.splitlines() if ln]
-        assert lines and all(ln.startswith("ntt ") for ln in lines)
+        assert lines and all(ln.startswith(("ntt ", "multi ")) for ln in lines)
         c2 = q.Context(0)
         try:
             c2.tune_import(table)
@@ -316,6 +316,58 @@ def test_uneven_workload_full_size(torch, ctx):
                 want = oracle.toeplitz_rows(xw[xo:xo + n // 64], n, seeds[sid], n + m - 1, r)
                 bits = oracle.unpack_bits(blk, m)
                 assert np.array_equal(bits[r], want), "block %d rows" % b
+    finally:
+        for sid in sids_l:
+            ctx.unregister_seed(sid)
+
+
+@pytest.mark.parametrize("estimate", [False, True])
+def test_plan_persistent_multiclass_equals_per_class(torch, ctx, estimate):
+    """The same uneven batch (transform lengths 2^12 .. 2^21) as the three
+    persistent multi-class launches and as per-class launches (chosen through
+    the tuning table), both as graphs replayed twice: identical bits, and
+    against the oracle; the multi-class form takes exactly three launches
+    (blocks shorter than 2^16 points join the 2^16 class)."""
+    import math as _m
+    log("plan persistent estimate=%d" % estimate)
+    rng = np.random.default_rng(31 + estimate)
+    nb = 60
+    ns = (64 * np.floor(2.0 ** rng.uniform(11, 20, nb) / 64)).astype(np.int64)
+    ns[:3] = [1 << 20, 64 * 97, 4096]
+    ms = np.array([int(n) if estimate else int(rng.integers(1, n + 1)) for n in ns])
+    L = 1 << 21
+    sids_l = [ctx.register_seed(dev(torch, qi.gen_seed_words(L, 60 + g)), L) for g in range(2)]
+    seeds = {sid: qi.gen_seed_words(L, 60 + g) for g, sid in enumerate(sids_l)}
+    sids = [sids_l[b % 2] for b in range(nb)]
+    rows, xwords, ywords = uneven_layout(ns, ms, sids)
+    if estimate:
+        samples = np.concatenate([qi.gen_adc(int(n) // 8, 8 + 32 * rng.random(), seed=500 + b)
+                                  for b, n in enumerate(ns)])
+        xw = qi.samples_as_words(samples)
+    else:
+        xw = qi.gen_bits(64 * xwords, 88)
+    x = dev(torch, xw)
+    key = "multi %d " % _m.ceil(_m.log2(nb))
+    outs = {}
+    try:
+        for form in (1, 0):
+            ctx.tune_import(key + str(form))
+            y = torch.full((ywords + 1,), -1, dtype=torch.int64, device="cuda:0")
+            m_out = torch.full((nb,), -1, dtype=torch.int64, device="cuda:0")
+            kw = {"m_out": m_out, "estimate": True} if estimate else {}
+            with ctx.plan(rows, x, y, graph=True, **kw) as pl:
+                info = pl.info()
+                pl.execute()
+                torch.cuda.synchronize()
+                if form == 1:                  # shorter classes join the 2^16 one
+                    assert info["launches"] == 3
+                pl.execute()                   # a replay gives the same bits
+                torch.cuda.synchronize()
+            outs[form] = (host(y), m_out.cpu().numpy())
+        assert np.array_equal(outs[0][0], outs[1][0])
+        assert np.array_equal(outs[0][1], outs[1][1])
+        m_of = [int(v) for v in outs[1][1]] if estimate else None
+        check_blocks(rows, xw, seeds, outs[1][0], m_of=m_of)
     finally:
         for sid in sids_l:
             ctx.unregister_seed(sid)
