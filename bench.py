@@ -42,6 +42,11 @@ PEAK_HBM = 8.0e12
 PEAK_INT8 = 5.0e15           # dense int8 MFMA
 
 
+def progress(msg):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def log2i(v):
     return int(v).bit_length() - 1
 
@@ -936,32 +941,40 @@ def main():
             hbm[k]["counter_GB/s"] = round(b / avg / 1e9, 1)
     out["ntt_hbm"] = hbm or None
     plain = value
+    progress("main workload done (%.2f Gbit/s)" % value)
     if args.uneven:
         out["uneven_4096"] = bench_uneven(ctx, q, torch, qi)
         out["uneven_4096"]["raw_vs_single_block_path"] = round(
             out["uneven_4096"]["raw_gbps"] / plain, 3)
         verified["uneven_plan_vs_plain_calls"] = out["uneven_4096"]["verified_vs_plain_calls"]
+        progress("uneven batch done")
     if args.sweep:
         out["sweep_2^30"] = bench_sweep(ctx, q, torch, qi)
         out["sweep_2^30"]["best_raw_vs_single_block_path"] = {
             k: round(max(v for kk, v in row.items() if isinstance(v, float)) / plain, 3)
             for k, row in out["sweep_2^30"]["by_block_bits"].items()}
         verified["sweep_paths_agree"] = out["sweep_2^30"]["verified_paths_agree"]
+        progress("sweep done")
     if args.modified:
         out["modified_toeplitz"] = bench_modified(ctx, q, torch, qi)
+        progress("modified hash done")
     if args.fft64:
         out["paper_method_fft64"] = bench_fft64(ctx, q, torch, qi)
         verified["fft64_equal_to_ntt"] = out["paper_method_fft64"]["verified_equal_to_ntt"]
+        progress("float64 method done")
     if args.estimator:
         out["estimator"] = bench_estimator(ctx, q, torch, qi)
+        progress("estimator done")
     if args.serve:
         out["serve"] = bench_serve(ctx, q, torch, qi)
+        progress("serving done")
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(xw, n, sw, m, args.cpu_seconds)
         out["cpu_paper_method"], k_oracle = cpu_paper_method(xw, n, sw, m)
         out["cpu_bitwise_n2^17"] = cpu_bitwise_config1(qi)
         out["host_cpu"] = host_cpu()
         verified["vs_oracle"] = bool(np.array_equal(y_host[:mw], k_oracle[:mw]))
+        progress("cpu baseline done")
     ctx.close()
     out["verified"] = all(verified.values())
     out["verification"] = verified

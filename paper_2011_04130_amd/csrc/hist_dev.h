@@ -487,8 +487,8 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
 
 // One of a.G counting workgroups of a launch that also does other work: it
 // stores its partial row, and the last of them to finish (a device-scope
-// ticket) sums the rows and runs the estimate, then clears the ticket for
-// the next launch.  The rows are published without a device-scope release
+// ticket) sums the rows and runs the estimate, then sets the ticket up for
+// the next call.  The rows are published without a device-scope release
 // fence, which would write back every dirty line of this die's L2 (the
 // other work's output streams through it): they are stored write-through
 // (device-scope atomic stores) and each thread waits until its stores have
@@ -498,26 +498,35 @@ __device__ void hist_finish_body(const HistArgs& a, FinishLds& L) {
 // rows.  lds: at least max(HCW * HB words,
 // sizeof(FinishLds)) bytes, 16-byte aligned.
 // The ticket word holds (tag, count): TICKET_COUNT_BITS low bits count the
-// workgroups of the call with that tag.  A workgroup that finds another
-// call's tag there (one that never completed) starts the count afresh, so a
-// stuck ticket cannot silence later calls.
+// workgroups of the call with that tag.  The last workgroup of a call leaves
+// the word at (next tag, 0), the tag the context's next call will carry, so
+// in the normal sequence every workgroup takes its ticket with one atomic
+// add.  A workgroup whose add finds another tag there (a replay with the
+// same tag, another context's sequence, or a launch that never completed)
+// joins through a compare-and-swap loop that starts the count afresh under
+// its own tag, so a stuck ticket cannot silence later calls.
 constexpr int TICKET_COUNT_BITS = 9;  // HIST_MAX_GROUPS = 256 fits
-static_assert(HIST_MAX_GROUPS < (1 << TICKET_COUNT_BITS), "ticket count field");
+constexpr uint32_t TICKET_TAG_MASK = (1u << (32 - TICKET_COUNT_BITS)) - 1;
+static_assert(2 * HIST_MAX_GROUPS <= (1 << TICKET_COUNT_BITS),
+              "ticket count field: a stale count below G plus G adds never carries into the tag");
 
 // Takes this workgroup's ticket; true for the last of the call's G.  Lock
 // free: a failed compare-and-swap means another workgroup's succeeded, so
-// the loop ends after at most G rounds.
+// the loop ends after at most G rounds.  The adds that land on a word with
+// another tag are discarded when the loop replaces that word.
 __device__ inline bool take_ticket(uint32_t* ticket, uint32_t epoch, uint32_t G) {
   constexpr uint32_t CM = (1u << TICKET_COUNT_BITS) - 1;
   const uint32_t tag = epoch << TICKET_COUNT_BITS;
-  uint32_t old = __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (uint32_t k = 0; k <= G; ++k) {
+  uint32_t old = atomicAdd(ticket, 1u);
+  if ((old & ~CM) == tag) return (old & CM) + 1u == G;
+  old = old + 1u;  // the word as this add left it (other adds may follow)
+  for (uint32_t k = 0; k <= 2 * G; ++k) {
     const uint32_t cnt = (old & ~CM) == tag ? (old & CM) : 0u;
     const uint32_t seen = atomicCAS(ticket, old, tag | (cnt + 1u));
     if (seen == old) return cnt + 1u == G;
     old = seen;
   }
-  return false;  // not reached: at most G - 1 other workgroups can win first
+  return false;  // not reached: each failed round is another workgroup's success or add
 }
 
 template <int NT, int HCW>
@@ -532,9 +541,17 @@ __device__ void estimate_workgroup(const HistArgs& a, uint32_t wg, uint32_t* tic
   if (lds[0] == 0u) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
-  hist_finish_body<NT>(a, *reinterpret_cast<FinishLds*>(lds));
-  // count back to 0 under the same tag, for a replay of this launch
-  if (threadIdx.x == 0) atomicExch(ticket, a.epoch << TICKET_COUNT_BITS);
+  FinishLds& L = *reinterpret_cast<FinishLds*>(lds);
+  hist_finish_body<NT>(a, L);
+  // the next call's tag with a zero count: its workgroups then take their
+  // tickets with one add each.  After a failed row check (a ticket that was
+  // not this call's alone) the word keeps this call's tag, so late adds of
+  // this call cannot leak into the next call's count: that call then starts
+  // afresh through the compare-and-swap loop.
+  if (threadIdx.x == 0) {
+    const uint32_t next = L.ok ? a.epoch + 1u : a.epoch;
+    atomicExch(ticket, (next & TICKET_TAG_MASK) << TICKET_COUNT_BITS);
+  }
 }
 
 }  // namespace hd

@@ -123,3 +123,35 @@ def test_failed_consistency_check_fails_closed(torch, ctx, fault):
         assert m2 == m0 and me2["h_mod"] == me0["h_mod"] and np.array_equal(y2, y0)
     finally:
         ctx.unregister_seed(sid)
+
+
+def test_extract_graph_replays_and_eager_calls_interleaved(torch, ctx):
+    """A captured qrng_extract carries one tag for every replay, while eager
+    calls between the replays move the context's tag on: each replay then
+    finds another call's tag on the ticket and must start its count afresh;
+    every replay and every eager call gives the same m and bits."""
+    c, sid, run = _extract_case(torch, ctx)
+    try:
+        m0, me0, y0 = run()
+        assert m0 == c["m_expected"]
+        st = torch.from_numpy(qi.gen_adc(c["S"], c["sigma"], seed=c["adc_seed"])).to("cuda:0")
+        n = c["n"]
+        y = torch.zeros((n + 63) // 64, dtype=torch.int64, device="cuda:0")
+        mo = torch.full((1,), -1, dtype=torch.int64, device="cuda:0")
+        ctx.extract(st, sid, n, y=y, m_out=mo)       # warm-up: workspaces exist before capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.extract(st, sid, n, y=y, m_out=mo)
+        for k in range(3):
+            y.zero_()
+            mo.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(mo.item()) == m0, "replay %d" % k
+            assert np.array_equal(y.cpu().numpy().view(np.uint64), y0), "replay %d" % k
+            for _ in range(k + 1):                   # eager calls move the tag on
+                m1, _, y1 = run()
+                assert m1 == m0 and np.array_equal(y1, y0)
+    finally:
+        ctx.unregister_seed(sid)
