@@ -250,6 +250,93 @@ __device__ __forceinline__ void mont_powers(const TwTables& tw, uint32_t e, uint
   }
 }
 
+// A radix-2 first round followed by a radix-16 round (columns of 2^9
+// points): the thread that owns round-1 groups (0, b) and (1, b) holds both
+// operands of every round-0 butterfly of them, so the two rounds run in
+// registers with no LDS exchange or barrier between them.
+template <int LOG1>
+constexpr bool merge01() {
+  return RP<LOG1>::lgr(0) == 1 && RP<LOG1>::K >= 3;
+}
+
+// Forward rounds 0 and 1 on input bits: bit q of this column is
+// (wbits[q] >> c) & 1.  Round 0 on bits x0 (position q) and x1 (q + N/2):
+// x0 + x1, and (x0 - x1) w_N^q = x0 w + x1 (p - w), no multiplication.
+// st(g, e, v) stores element e of round-1 group g.  b: round-1 group index
+// within its half, b < Geo<LOG1, 1>::s.
+template <int LOG1, class ST>
+__device__ __forceinline__ void fwd_round01_bits(int b, const uint2* __restrict__ tws,
+                                                 bool upper_zero,
+                                                 const uint32_t* __restrict__ wbits, int c,
+                                                 ST&& st) {
+  using G0 = Geo<LOG1, 0>;
+  using G1 = Geo<LOG1, 1>;
+  static_assert(G0::r == 2 && G1::r == 16 && G0::s == 16 * G1::s, "radix 2 then radix 16");
+  uint32_t v[2][16];
+  if (upper_zero) {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int q = a * G1::s + b;
+      const uint32_t x0 = (wbits[q] >> c) & 1u;
+      v[0][a] = x0;
+      v[1][a] = x0 ? tws[G0::toff + 2 * q + 1].x : 0u;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int q = a * G1::s + b;
+      const uint32_t w = tws[G0::toff + 2 * q + 1].x;  // w_N^q, N = 2^LOG1
+      const uint32_t x0 = (wbits[q] >> c) & 1u, x1 = (wbits[q + G0::s] >> c) & 1u;
+      v[0][a] = x0 + x1;
+      v[1][a] = (x0 ? w : 0u) + (x1 ? P - w : 0u);
+    }
+  }
+  uint2 t[16];
+  group_tw<16, G1::s, false>(tws + G1::toff, b, t);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    dft_reg<16, false, true>(v[h]);
+#pragma unroll
+    for (int a = 1; a < 16; ++a) v[h][a] = mul_shoup(v[h][a], t[a].x, t[a].y);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < 16; ++a) st(h * G1::s + b, a, v[h][a]);
+}
+
+// Inverse rounds 1 and 0 (the last two of a column): ld(g, e) reads element e
+// of round-1 group g; out(q, e, v) receives position q + e N/2 (e = 0, 1).
+// The upper outputs are formed only when need_hi.
+template <int LOG1, class LD, class OUT>
+__device__ __forceinline__ void inv_round10(int b, const uint2* __restrict__ tws, bool need_hi,
+                                            LD&& ld, OUT&& out) {
+  using G0 = Geo<LOG1, 0>;
+  using G1 = Geo<LOG1, 1>;
+  static_assert(G0::r == 2 && G1::r == 16 && G0::s == 16 * G1::s, "radix 16 then radix 2");
+  uint32_t v[2][16];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[h][a] = ld(h * G1::s + b, a);
+  uint2 t[16];
+  group_tw<16, G1::s, false>(tws + G1::toff, b, t);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int a = 1; a < 16; ++a) v[h][a] = mul_shoup(v[h][a], t[a].x, t[a].y);
+    dft_reg<16, true>(v[h]);
+  }
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int q = a * G1::s + b;
+    const uint2 w = tws[G0::toff + 2 * q + 1];  // w_N^-q
+    const uint32_t u = v[0][a], tt = mul_shoup(v[1][a], w.x, w.y);
+    out(q, 0, red2(u + tt));
+    if (need_hi) out(q, 1, sub2(u, tt));
+  }
+}
+
 // ----------------------------------------------------------------- pass A
 struct ColFwdArgs {
   const uint32_t* bits;
@@ -265,6 +352,9 @@ struct ColFwdArgs {
   // hg > 0: workgroups x < hg of item 0 count samples for the min-entropy
   // estimate instead (those of other items exit), the last of them runs it
   uint32_t hg;
+  // nonzero: every source bit at positions q >= Nc/2 is 0 (the chunks of the
+  // split transform), so the first radix-2 round skips those inputs
+  uint32_t upper_zero;
   uint32_t* ticket;
   hd::HistArgs est;
 };
@@ -272,13 +362,13 @@ struct ColFwdArgs {
 constexpr int COLS = 32;  // columns per workgroup (128-byte rows)
 constexpr int CGMAX = 2;  // groups in flight per thread
 // slots (threads per column) of a column workgroup, 32 columns each: 16
-// (512 threads), and 32 for the inverse 2^9-point columns, where the extra
-// waves hide more of the input loads and barriers (one group per thread in
-// the radix-16 rounds).  The forward pass keeps 512: its estimate workgroups
-// need more registers, and at 1024 threads only one workgroup would fit a CU.
+// (512 threads, two workgroups per CU).  Inverse 2^9-point columns once ran
+// 32 slots (the extra waves hid more of the input loads and barriers); with
+// their last two rounds merged in registers (inv_round10) a thread holds 32
+// values there, and 16 slots keep two workgroups per CU.
 template <int LOG1, bool INV>
 constexpr int cslots() {
-  return INV && LOG1 >= 9 ? 32 : 16;
+  return 16;
 }
 
 // sub-histogram copies of an estimate workgroup in the column LDS
@@ -288,8 +378,11 @@ constexpr int est_copies() {
 }
 
 // Pass A on column block bx of item `item` (NS slots of 32 threads; lds:
-// (1 << LOG1) * COLS words, wbits: 1 << LOG1 words).
-template <int LOG1, int NS>
+// (1 << LOG1) * COLS words, wbits: 1 << LOG1 words).  MERGE: run the first
+// two rounds as one register round where they allow it (merge01); the
+// persistent kernels keep them apart (their register budget is shared by
+// every column length).
+template <int LOG1, int NS, bool MERGE = true>
 __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTables& tw, int bx,
                                               int item, uint32_t* __restrict__ lds,
                                               uint32_t* __restrict__ wbits) {
@@ -344,7 +437,7 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
     const uint32_t t = e ? mul_mont(bg, upow[brev<GL::lgr>(e)]) : bg;
     out[((uint32_t)p << l2) + j2] = mul_mont(v, t);
   };
-  static_for<0, K>([&](auto kc) {
+  auto round = [&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if constexpr (K == 1)
       round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_bits, st_out);
@@ -355,7 +448,16 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
     else
       round_all<LOG1, k, NS, CGMAX, false>(slot, tw.fwd, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k < K - 1) __syncthreads();
-  });
+  };
+  if constexpr (MERGE && merge01<LOG1>()) {
+    for (int b = slot; b < Geo<LOG1, 1>::s; b += NS)
+      fwd_round01_bits<LOG1>(b, tw.fwd, a.upper_zero != 0, wbits, c,
+                             st_lds_k(std::integral_constant<int, 1>{}));
+    __syncthreads();
+    static_for<2, K>(round);
+  } else {
+    static_for<0, K>(round);
+  }
 }
 
 template <int LOG1>
@@ -402,8 +504,9 @@ __device__ __forceinline__ uint64_t valid_bits(uint64_t m, const uint64_t* m_dev
 }
 
 // Pass C on column block bx of item `item` (NS slots of 32 threads; lds:
-// (1 << LOG1) * COLS words).
-template <int LOG1, int NS>
+// (1 << LOG1) * COLS words).  MERGE as in cols_fwd_body, for the last two
+// rounds.
+template <int LOG1, int NS, bool MERGE = true>
 __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTables& tw, int bx,
                                               int item, uint32_t* __restrict__ lds) {
   const int c = threadIdx.x & (COLS - 1), slot = threadIdx.x >> 5;
@@ -468,7 +571,7 @@ __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTable
     const int32_t t0 = t - c;
     if ((lane & 31) == 0 && t0 < ylimit) ywords[t0 >> 5] = lane ? (uint32_t)(bal >> 32) : (uint32_t)bal;
   };
-  static_for_down<0, K>([&](auto kc) {
+  auto round = [&](auto kc) {
     constexpr int k = decltype(kc)::value;
     if constexpr (K == 1)
       round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_in, st_bits);
@@ -479,7 +582,16 @@ __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTable
     else
       round_all<LOG1, k, NS, CGMAX, true>(slot, tw.inv, ld_lds_k(kc), st_lds_k(kc));
     if constexpr (k > 0) __syncthreads();
-  });
+  };
+  if constexpr (MERGE && merge01<LOG1>()) {
+    static_for_down<2, K>(round);
+    // outputs at j1 >= N1/2 lie at bit t >= (N1/2) N2 of the chunk
+    const bool need_hi = ((int64_t)Geo<LOG1, 0>::s << l2) < (int64_t)ylimit;
+    for (int b = slot; b < Geo<LOG1, 1>::s; b += NS)
+      inv_round10<LOG1>(b, tw.inv, need_hi, ld_lds_k(std::integral_constant<int, 1>{}), st_bits);
+  } else {
+    static_for_down<0, K>(round);
+  }
 }
 
 template <int LOG1>
@@ -936,7 +1048,7 @@ __global__ __launch_bounds__(MC_T_COLS, 4) void k_mc_cols_fwd(const McDev* __res
     const int item = (int)(local / C.per[0]), tile = (int)(local % C.per[0]);
     const TwTables t = fresh_tables(tw);
     static_switch<MC_MIN_LOG1, MC_MAX_LOG1>(C.log1, [&](auto l) {
-      cols_fwd_body<decltype(l)::value, MC_NS>(C.fa, t, tile, item, lds, wbits);
+      cols_fwd_body<decltype(l)::value, MC_NS, false>(C.fa, t, tile, item, lds, wbits);
     });
   }
 }
@@ -1001,7 +1113,7 @@ __global__ __launch_bounds__(MC_T_COLS, 4) void k_mc_cols_inv(const McDev* __res
     const int item = (int)(local / C.per[2]), tile = (int)(local % C.per[2]);
     const TwTables t = fresh_tables(tw);
     static_switch<MC_MIN_LOG1, MC_MAX_LOG1>(C.log1, [&](auto l) {
-      cols_inv_body<decltype(l)::value, MC_NS>(C.ic, t, tile, item, lds);
+      cols_inv_body<decltype(l)::value, MC_NS, false>(C.ic, t, tile, item, lds);
     });
   }
 }
@@ -1270,6 +1382,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
     c.map[k] = BitMap{(int32_t)lo, (int32_t)lo, (int32_t)hi, (int32_t)Nc};
   }
   if (p.nx == 1 && p.ny == 1) c.map[0] = rotated_block((uint32_t)n, (int32_t)Nc);
+  else c.upper_zero = 2 * p.bx <= Nc;  // chunk k covers positions q < bx only
   c.nmap = p.nx;
   c.log2 = p.log2;
   c.log_nc = p.log_nc;
