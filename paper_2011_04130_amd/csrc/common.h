@@ -69,6 +69,17 @@ __device__ __forceinline__ uint32_t mul_mont(uint32_t a, uint32_t b) {
   return hi + mh + (lo != 0u);
 }
 
+// Montgomery product with a factor t fixed ahead of time: with
+// tp = t (-p^-1) mod 2^32, the reduction multiplier (a t)(-p^-1) mod 2^32 is
+// a tp mod 2^32, so a t 2^-32 mod p takes three multiplications instead of
+// four.  (a t + m p) / 2^32 is exact; its low-word carry is 1 exactly when
+// m != 0 (p is odd).  Result in [0, 2p) for a t < 2^32 p.
+__device__ __forceinline__ uint32_t mont_pre(uint32_t t) { return t * NPINV; }
+__device__ __forceinline__ uint32_t mul_mont_pre(uint32_t a, uint32_t t, uint32_t tp) {
+  const uint32_t m = a * tp;
+  return __umulhi(a, t) + __umulhi(m, P) + (m != 0u);
+}
+
 constexpr int ilog2(uint32_t v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 constexpr uint32_t bitrev(uint32_t v, int bits) {
   uint32_t r = 0;

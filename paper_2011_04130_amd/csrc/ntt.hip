@@ -428,14 +428,23 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
   // B_g U^bitrev(e) with U = w_Nc^(j2 2^(LOG1-lgr)) fixed per thread
   using GL = Geo<LOG1, K - 1>;
   static_assert(GL::s == 1, "last round works on contiguous groups");
-  uint32_t upow[GL::r];
+  // (v U^f 2^-32) B_g 2^-32 with Montgomery-form U^f and B_g: both factors
+  // are fixed before the values arrive, so both products take the
+  // three-multiplication form (U^0 is the Montgomery one: skipped)
+  uint32_t upow[GL::r], upre[GL::r];
   mont_powers<GL::r>(tw, (gstep << (LOG1 - GL::lgr)) & ((1u << LOG_MAX) - 1), upow);
-  uint32_t bg = 0;
+#pragma unroll
+  for (int f = 0; f < GL::r; ++f) upre[f] = mont_pre(upow[f]);
+  uint32_t bg = 0, bgp = 0;
   auto st_out = [&](int g, int e, uint32_t v) {
     const int p = g * GL::r + e;
-    if (e == 0) bg = gtw(tw, gstep * (uint32_t)brev<LOG1 - GL::lgr>(g));
-    const uint32_t t = e ? mul_mont(bg, upow[brev<GL::lgr>(e)]) : bg;
-    out[((uint32_t)p << l2) + j2] = mul_mont(v, t);
+    if (e == 0) {
+      bg = gtw(tw, gstep * (uint32_t)brev<LOG1 - GL::lgr>(g));
+      bgp = mont_pre(bg);
+    }
+    const int f = brev<GL::lgr>(e);
+    const uint32_t x = e ? mul_mont_pre(v, upow[f], upre[f]) : v;
+    out[((uint32_t)p << l2) + j2] = mul_mont_pre(x, bg, bgp);
   };
   auto round = [&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -540,14 +549,21 @@ __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTable
   // inverse four-step twiddle, factored as in pass A
   using GL = Geo<LOG1, K - 1>;
   static_assert(GL::s == 1, "last round works on contiguous groups");
-  uint32_t upow[GL::r];
+  uint32_t upow[GL::r], upre[GL::r];
   mont_powers<GL::r>(tw, (0u - (gstep << (LOG1 - GL::lgr))) & EMASK, upow);
-  uint32_t bg = 0;
+#pragma unroll
+  for (int f = 0; f < GL::r; ++f) upre[f] = mont_pre(upow[f]);
+  uint32_t bg = 0, bgp = 0;
   auto ld_in = [&](int g, int e) -> uint32_t {
     const int p = g * GL::r + e;
-    if (e == 0) bg = gtw(tw, (0u - gstep * (uint32_t)brev<LOG1 - GL::lgr>(g)) & EMASK);
-    const uint32_t t = e ? mul_mont(bg, upow[brev<GL::lgr>(e)]) : bg;
-    return mul_mont(in[((uint32_t)p << l2) + j2], t);
+    if (e == 0) {
+      bg = gtw(tw, (0u - gstep * (uint32_t)brev<LOG1 - GL::lgr>(g)) & EMASK);
+      bgp = mont_pre(bg);
+    }
+    const int f = brev<GL::lgr>(e);
+    const uint32_t v = in[((uint32_t)p << l2) + j2];
+    const uint32_t x = e ? mul_mont_pre(v, upow[f], upre[f]) : v;
+    return mul_mont_pre(x, bg, bgp);
   };
   auto ld_lds_k = [&](auto kc) {
     return [&](int g, int e) -> uint32_t {
