@@ -688,6 +688,16 @@ def bench_serve(ctx, q, torch, qi, seconds=0.6, nwin=64, min_requests=10000):
     return res
 
 
+def bench_issue(ctx, q, torch, qi):
+    """Cycles one SIMD spends per wave64 instruction of single VALU ops
+    (the library's probe kernels; 4.0 is the nominal 16-lane rate that the
+    ALU peaks of this line assume)."""
+    return {"cycles_per_wave_instruction": ctx.issue_rates(2.4), "clock_ghz": 2.4,
+            "nominal": 4.0,
+            "note": "independent chains, 8 waves per SIMD, HIP-event timed; "
+                    "a rate below 4.0 issues faster than the nominal VALU peak"}
+
+
 def bench_counters(ctx, q, torch, qi):
     """A short fixed sequence for hardware-counter runs (rocprofv3 --pmc):
     three qrng_extract steps on the n = 2^23 block (the three transform
@@ -751,7 +761,7 @@ def main():
     ap.add_argument("--estimator", type=int, default=1,
                     help="also time the subset estimate and run the attacked-detector source")
     ap.add_argument("--only", choices=["uneven", "sweep", "serve", "modified", "fft64",
-                                       "estimator", "counters"],
+                                       "estimator", "counters", "issue"],
                     help="run just this extra workload and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
@@ -781,7 +791,8 @@ def main():
         ctx = q.Context(0)
         fn = {"uneven": bench_uneven, "sweep": bench_sweep, "serve": bench_serve,
               "modified": bench_modified, "fft64": bench_fft64,
-              "estimator": bench_estimator, "counters": bench_counters}[args.only]
+              "estimator": bench_estimator, "counters": bench_counters,
+              "issue": bench_issue}[args.only]
         print(json.dumps(fn(ctx, q, torch, qi)))
         ctx.close()
         return
@@ -919,6 +930,7 @@ def main():
             "direct": round(n / t_direct / 1e9, 4)}
         # the direct product on the same block: m n GF(2) MACs, 32 per bit op
         bitops = m * n / 32.0 / t_direct
+        out["valu_issue"] = bench_issue(ctx, q, torch, qi)
         out["direct_roofline"] = {"bound": "alu", "achieved": round(bitops / 1e12, 3),
                                   "peak": PEAK_BITOP / 1e12, "unit": "T bitop/s",
                                   "frac": round(bitops / PEAK_BITOP, 4),

@@ -502,6 +502,19 @@ qrng_status qrng_profile_query(qrng_ctx *ctx, int kernel_id, uint64_t *launches,
 /* Forget the recorded launches (waits for them first). */
 qrng_status qrng_profile_reset(qrng_ctx *ctx);
 
+/* Issue cost of single VALU instructions on this device, for the ALU
+ * rooflines: cycles_out[i], i < min(n, QRNG_PROBE_OPS), receives the
+ * shader-clock cycles one SIMD spends per wave64 instruction of op i (named
+ * by qrng_profile_issue_op_name), measured with a kernel of independent
+ * chains that keeps eight waves on every SIMD, timed with HIP events and
+ * converted at clock_ghz (the device's peak shader clock, 2.4 on MI355X).
+ * 4.0 is the nominal rate of a 16-lane SIMD.  Synchronous on `stream`;
+ * allocates a small device buffer for the duration of the call. */
+#define QRNG_PROBE_OPS 8
+qrng_status qrng_profile_issue_rates(qrng_ctx *ctx, double clock_ghz, double *cycles_out,
+                                     int n, void *stream);
+const char *qrng_profile_issue_op_name(int op);
+
 #ifdef __cplusplus
 }
 #endif

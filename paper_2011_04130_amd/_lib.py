@@ -101,7 +101,8 @@ EXPORTS = ["qrng_version", "qrng_last_error", "qrng_create", "qrng_destroy",
            "qrng_server_window",
            "qrng_server_query", "qrng_server_destroy",
            "qrng_profile_enable", "qrng_profile_kernel_name",
-           "qrng_profile_query", "qrng_profile_reset"]
+           "qrng_profile_query", "qrng_profile_reset",
+           "qrng_profile_issue_rates", "qrng_profile_issue_op_name"]
 
 
 def load_library(path: str | None = None):
@@ -198,6 +199,11 @@ def load_library(path: str | None = None):
     lib.qrng_profile_query.restype = i32
     lib.qrng_profile_reset.argtypes = [vp]
     lib.qrng_profile_reset.restype = i32
+    lib.qrng_profile_issue_rates.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                             i32, vp]
+    lib.qrng_profile_issue_rates.restype = i32
+    lib.qrng_profile_issue_op_name.argtypes = [i32]
+    lib.qrng_profile_issue_op_name.restype = ctypes.c_char_p
     if path is None:
         _lib = lib
     return lib

@@ -99,6 +99,21 @@ class Context:
                 out[name] = (int(cnt.value), float(ms.value))
         return out
 
+    def issue_rates(self, clock_ghz: float = 2.4, stream=None) -> dict:
+        """{instruction: cycles per wave64 instruction per SIMD}, measured on
+        the device by the library's probe kernels (4.0 = the nominal rate)."""
+        import torch
+        n = 8
+        buf = (ctypes.c_double * n)()
+        check(self._lib.qrng_profile_issue_rates(self._h, float(clock_ghz), buf, n,
+                                                 _stream(torch, self.device, stream)))
+        out = {}
+        for i in range(n):
+            nm = self._lib.qrng_profile_issue_op_name(i)
+            if nm:
+                out[nm.decode()] = round(float(buf[i]), 3)
+        return out
+
     # -- Sec. II ------------------------------------------------------------
     def minentropy(self, samples, sample_bits: int = 8, model: int = MODEL_FIT,
                    mu: float = 0.0, sigma: float = 0.0, u_mode: int = U_MODEL_ARGMAX,

@@ -20,7 +20,7 @@ LIB = os.path.join(BUILD, "libqrng.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["ntt.hip", "direct.hip", "hist.hip", "mfma.hip", "modified.hip", "fft64.hip", "batch.hip",
-           "qrng.cpp", "server.cpp"]
+           "probe.hip", "qrng.cpp", "server.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -166,6 +166,16 @@ __device__ __forceinline__ void dft_reg(uint32_t (&v)[R]) {
   }
 }
 
+// Word i of a uniform base pointer, i < 2^30: the byte offset is formed in
+// 32 bits, so the access takes the scalar-base, 32-bit-offset address form
+// instead of 64-bit address arithmetic per lane.
+__device__ __forceinline__ uint32_t ld_w32(const uint32_t* __restrict__ base, uint32_t i) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
+__device__ __forceinline__ void st_w32(uint32_t* __restrict__ base, uint32_t i, uint32_t v) {
+  *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
+}
+
 // bit b of a 32-bit-word bit string (caller guarantees the word exists)
 __device__ __forceinline__ uint32_t get_bit(const uint32_t* __restrict__ w, uint64_t b) {
   return (w[b >> 5] >> (b & 31)) & 1u;

@@ -269,6 +269,16 @@ struct MeBatchArgs {
 };
 hipError_t minentropy_blocks(const MeBatchArgs& a, int nblocks, hipStream_t s);
 
+// ------------------------------------------------- issue-cost probe
+constexpr int PROBE_OPS = 8;
+const char* probe_op_name(int op);
+// words of the probe's output buffer for a device of num_cus CUs
+uint64_t probe_out_words(int num_cus);
+// Cycles per wave64 instruction per SIMD of probe op `op` at clock_ghz
+// (synchronous on s; out: probe_out_words words of device memory).
+hipError_t probe_issue_cycles(int op, int num_cus, double clock_ghz, uint32_t* out,
+                              hipStream_t s, double* cycles);
+
 // ------------------------------------------------- context services
 // (for the serving loop, which is built on the C ABI)
 int ctx_num_cus(const qrng_ctx* c);

@@ -444,7 +444,7 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
     }
     const int f = brev<GL::lgr>(e);
     const uint32_t x = e ? mul_mont_pre(v, upow[f], upre[f]) : v;
-    out[((uint32_t)p << l2) + j2] = mul_mont_pre(x, bg, bgp);
+    st_w32(out, ((uint32_t)p << l2) + j2, mul_mont_pre(x, bg, bgp));
   };
   auto round = [&](auto kc) {
     constexpr int k = decltype(kc)::value;
@@ -561,7 +561,7 @@ __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTable
       bgp = mont_pre(bg);
     }
     const int f = brev<GL::lgr>(e);
-    const uint32_t v = in[((uint32_t)p << l2) + j2];
+    const uint32_t v = ld_w32(in, ((uint32_t)p << l2) + j2);
     const uint32_t x = e ? mul_mont_pre(v, upow[f], upre[f]) : v;
     return mul_mont_pre(x, bg, bgp);
   };

@@ -483,6 +483,27 @@ qrng_status qrng_profile_reset(qrng_ctx* ctx) {
 }
 
 
+qrng_status qrng_profile_issue_rates(qrng_ctx* ctx, double clock_ghz, double* cycles_out, int n,
+                                     void* stream) {
+  if (!ctx || !cycles_out || n < 0) return fail(QRNG_EINVAL, "null argument");
+  if (!(clock_ghz > 0)) return fail(QRNG_EINVAL, "clock must be positive");
+  static_assert(QRNG_PROBE_OPS == PROBE_OPS, "probe op count");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* out = nullptr;
+  if (hipMalloc(&out, probe_out_words(ctx->num_cus) * 4) != hipSuccess)
+    return fail(QRNG_ENOMEM, "probe buffer");
+  hipError_t e = hipSuccess;
+  for (int op = 0; op < n && op < PROBE_OPS && e == hipSuccess; ++op)
+    e = probe_issue_cycles(op, ctx->num_cus, clock_ghz, out, s, &cycles_out[op]);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(out);
+  if (e != hipSuccess) return fail(QRNG_EDEVICE, "probe launch: %s", hipGetErrorString(e));
+  return QRNG_OK;
+}
+
+const char* qrng_profile_issue_op_name(int op) { return probe_op_name(op); }
+
 const char* qrng_version(void) { return "libqrng 0.1 (gfx950)"; }
 
 const char* qrng_last_error(void) { return g_err.c_str(); }
