@@ -17,6 +17,20 @@ namespace host {
 
 inline double phi(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
 
+// The counts of an estimate over every sample: the K bins plus the
+// out-of-range bin must add up to the S samples counted, else a partial
+// histogram was lost or counted twice and the estimate must not be used.
+inline bool counts_consistent(const unsigned long long* c, int K, unsigned long long oob,
+                              uint64_t S) {
+  if (oob > S) return false;
+  unsigned long long t = oob;
+  for (int v = 0; v < K; ++v) {
+    if (c[v] > S - t) return false;  // also catches wrap-around
+    t += c[v];
+  }
+  return t == S;
+}
+
 constexpr double kTieRel = 1e-9;  // relative closeness treated as a tie of model bins
 
 // Sec. II on the host: model P, H_min, d_U, Delta H_m, H_modify.

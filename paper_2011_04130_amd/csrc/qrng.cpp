@@ -623,7 +623,8 @@ qrng_status qrng_minentropy_subset(qrng_ctx* ctx, const uint8_t* samples, uint64
                         subset_seed, keep_thr, ctx->est_epoch, fm == FAULT_ROWS ? 1u : 0u));
   HIP_TRY(hipMemcpyAsync(ctx->counts_host, ctx->counts_dev, (K + 2) * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (ctx->counts_host[K + 1] != 1)
+  if (ctx->counts_host[K + 1] != 1 ||
+      (!keep_thr && !host::counts_consistent(ctx->counts_host, K, ctx->counts_host[K], S)))
     return fail(QRNG_EDEVICE, "the partial histograms failed their consistency check");
   if (ctx->counts_host[K])
     return fail(QRNG_EINVAL, "%llu samples are >= 2^%d", ctx->counts_host[K], N);

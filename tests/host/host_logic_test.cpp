@@ -99,6 +99,13 @@ int main() {
       std::printf("finish %.17g %.17g %.17g %.17g %.17g %.17g %.17g %u\n", r.mu_hat,
                   r.sigma_hat, r.h_min, r.h_actual, r.d_u, r.delta_h_m, r.h_mod,
                   r.argmax_model);
+    } else if (cmd == "counts") {
+      int K;
+      unsigned long long oob, S;
+      is >> K >> oob >> S;
+      std::vector<unsigned long long> c(K);
+      for (auto& v : c) is >> v;
+      std::printf("counts %d\n", qrng::host::counts_consistent(c.data(), K, oob, S) ? 1 : 0);
     } else if (cmd == "bits") {
       unsigned long long n;
       int N;

@@ -114,3 +114,29 @@ def test_oracle_selfcheck_under_sanitizers(tmp_path):
                   os.path.join(ROOT, "oracle", "toeplitz_oracle.c"), "-lm"])
     out = _run(exe, "")
     assert any(ln.startswith("oracle selfcheck ok") for ln in out), out
+
+
+def test_counts_consistency_guard(driver):
+    """The host's guard on a full estimate's counts: bins + out-of-range
+    must equal the samples counted; a lost or doubled partial histogram, or
+    counts that wrap, fail it."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for K in (2, 32, 256):
+        c = rng.integers(0, 1000, size=K)
+        oob = int(rng.integers(0, 5))
+        S = int(c.sum()) + oob
+        cases.append((K, oob, S, c, 1))                        # consistent
+        cases.append((K, oob, S + 1, c, 0))                    # one sample missing
+        cases.append((K, oob, S - 1, c, 0))                    # one counted twice
+        d = c.copy(); d[K // 2] += 17
+        cases.append((K, oob, S, d, 0))                        # a row added twice
+        cases.append((K, oob + 3, S, c, 0))                    # out-of-range miscounted
+    big = np.zeros(4, dtype=np.uint64); big[0] = np.uint64(2**64 - 1); big[1] = np.uint64(5)
+    cases.append((4, 0, 4, big, 0))                            # wraps to a small total
+    cases.append((4, 0, 0, np.zeros(4, dtype=np.uint64), 1))   # empty estimate is consistent
+    cases.append((4, 10, 5, np.zeros(4, dtype=np.uint64), 0))  # more out of range than samples
+    text = "".join("counts %d %d %d %s\n" % (K, oob, S, " ".join(str(int(v)) for v in c))
+                   for K, oob, S, c, _ in cases)
+    out = [ln for ln in _run(driver, text) if ln.startswith("counts")]
+    assert [int(ln.split()[1]) for ln in out] == [want for *_, want in cases]
