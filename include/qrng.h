@@ -369,8 +369,12 @@ void qrng_plan_destroy(qrng_plan *plan);
 /* The context's tuning table as text, one line per entry
  * "ntt <log2 Nc> <ceil log2 class size> <shape>" (shape: log2 of the
  * per-launch workspace cap in bytes, 40 = none, -1 = one direct launch per
- * block).  *len receives the length without the terminating 0; buf
- * (nullable) receives the text if cap > len. */
+ * block) or "multi <ceil log2 block count> <form>" (1 = the persistent
+ * three-launch form, 0 = per-class launches).  An entry that a tuning run
+ * of this context measured is followed by a comment line
+ * "# <entry key> measured <shape>:<ms> ..." with the time of every
+ * candidate (qrng_tune_import skips '#' lines).  *len receives the length
+ * without the terminating 0; buf (nullable) receives the text if cap > len. */
 qrng_status qrng_tune_export(qrng_ctx *ctx, char *buf, uint64_t cap, uint64_t *len);
 
 /* Merge a table written by qrng_tune_export (EINVAL on a malformed line,

@@ -361,15 +361,20 @@ struct ColFwdArgs {
 
 constexpr int COLS = 32;  // columns per workgroup (128-byte rows)
 constexpr int CGMAX = 2;  // groups in flight per thread
-// slots (threads per column) of a column workgroup, 32 columns each: 16
-// (512 threads, two workgroups per CU).  Inverse 2^9-point columns once ran
-// 32 slots (the extra waves hid more of the input loads and barriers); with
-// their last two rounds merged in registers (inv_round10) a thread holds 32
-// values there, and 16 slots keep two workgroups per CU.
+// slots (threads per column) of a column workgroup, 32 columns each: enough
+// for two radix-16 groups of the last round per thread, 2^LOG1 / 32 (16 slots,
+// 512 threads, for 2^9-point columns; 2 for 2^6), at least 2.  With one slot
+// per last-round group the short columns left half or more of their threads
+// idle in that round and paid the per-thread twiddle set-up for 16 values.
+// (Inverse 2^9-point columns once ran 32 slots, the extra waves hiding more
+// of the input loads and barriers; with their last two rounds merged in
+// registers, inv_round10, 16 slots keep two workgroups per CU.)
 template <int LOG1, bool INV>
 constexpr int cslots() {
-  return 16;
+  return LOG1 >= 9 ? 16 : ((1 << LOG1) / 32 > 2 ? (1 << LOG1) / 32 : 2);
 }
+// the estimate workgroups inside pass A need 256 threads (one per bin)
+constexpr int EST_MIN_LOG1 = 8;
 
 // sub-histogram copies of an estimate workgroup in the column LDS
 template <int LOG1>
@@ -476,7 +481,8 @@ __global__ __launch_bounds__((COLS * cslots<LOG1, false>())) void k_cols_fwd(Col
   __shared__ __align__(16) uint32_t lds[(1 << LOG1) * COLS];
   __shared__ uint32_t wbits[1 << LOG1];  // row j1's 32 input bits of this column block
   if (blockIdx.x < a.hg) {
-    if constexpr (LOG1 >= 7) {
+    if constexpr (LOG1 >= EST_MIN_LOG1) {
+      static_assert(COLS * NS >= 256, "one estimate thread per bin");
       static_assert(est_copies<LOG1>() * hd::HB <= (1 << LOG1) * COLS &&
                         sizeof(hd::FinishLds) <= sizeof(lds),
                     "estimate workgroup fits the column LDS");
@@ -1443,7 +1449,7 @@ hipError_t ntt_hash(const NttPlan& p, const uint32_t* x_bits, uint64_t n, uint64
   return cols_inv(p.log1, ci, dim3((1u << p.log2) / COLS, batch * p.ny), tw, s);
 }
 
-bool ntt_fuses_estimate(const NttPlan& p) { return p.log1 >= 7; }
+bool ntt_fuses_estimate(const NttPlan& p) { return p.log1 >= EST_MIN_LOG1; }
 
 bool ntt_plan_for_length(int log_nc, NttPlan* p) {
   if (log_nc < 10 || log_nc > LOG_MAX) return false;

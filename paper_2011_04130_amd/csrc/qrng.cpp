@@ -166,6 +166,8 @@ struct qrng_ctx {
   // of the class size) -> sub-batch workspace cap as log2 bytes, or
   // kTuneDirect for one direct launch per block
   std::map<std::pair<int, int>, int> tune;
+  // the times (ms) of every candidate the last tuning run measured, per key
+  std::map<std::pair<int, int>, std::vector<std::pair<int, float>>> tune_ms;
 };
 
 namespace {
@@ -1423,6 +1425,8 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
       float best = INFINITY;
       int best_c = choice[k];
       int last_chunk = -1;
+      auto& meas = ctx->tune_ms[{c.log_nc, tune_key_count(c.ids.size())}];
+      meas.clear();
       for (int cc : cand) {
         NttPlan np;
         ntt_plan_for_length(c.log_nc, &np);
@@ -1440,6 +1444,7 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
         float ms = 0;
         e = time_steps(st, s, &ms);
         if (e) return bail(e);
+        meas.emplace_back(cc, ms);
         if (ms < best) best = ms, best_c = cc;
       }
       choice[k] = best_c;
@@ -1617,6 +1622,7 @@ qrng_status qrng_plan_create(qrng_ctx* ctx, const qrng_block* blocks, uint32_t n
       if (e) return bail(e);
       use_multi = t_multi <= t_each;
       ctx->tune[key] = use_multi ? 1 : 0;
+      ctx->tune_ms[key] = {{0, t_each}, {1, t_multi}};
     }
     if (use_multi) {
       pl->steps = multi;
@@ -1702,6 +1708,20 @@ qrng_status qrng_tune_export(qrng_ctx* ctx, char* buf, uint64_t cap, uint64_t* l
       os << "multi " << kv.first.second << " " << kv.second << "\n";
     else
       os << "ntt " << kv.first.first << " " << kv.first.second << " " << kv.second << "\n";
+    // what the last tuning run measured for this key, as comment lines
+    // ("# <line> measured <choice>:<ms> ..."), which qrng_tune_import skips
+    auto m = ctx->tune_ms.find(kv.first);
+    if (m != ctx->tune_ms.end() && !m->second.empty()) {
+      os << "# " << (kv.first.first == 0 ? "multi" : "ntt");
+      if (kv.first.first) os << " " << kv.first.first;
+      os << " " << kv.first.second << " measured";
+      for (auto& cm : m->second) {
+        char t[48];
+        std::snprintf(t, sizeof t, " %d:%.3f", cm.first, (double)cm.second);
+        os << t;
+      }
+      os << "\n";
+    }
   }
   const std::string t = os.str();
   *len = t.size();

@@ -185,11 +185,25 @@ def test_plan_tune_table_roundtrip(torch, ctx):
             check_blocks(rows, xw, {sid: sw}, host(y))
         table = ctx.tune_export()
         lines = [ln for ln in table.splitlines() if ln]
-        assert lines and all(ln.startswith(("ntt ", "multi ")) for ln in lines)
+        entries = [ln for ln in lines if not ln.startswith("#")]
+        assert entries and all(ln.startswith(("ntt ", "multi ")) for ln in entries)
+        # the measured alternatives follow their entry; the choice is the fastest
+        measured = {}
+        for ln in lines:
+            if ln.startswith("#"):
+                key, _, rest = ln[2:].partition(" measured ")
+                measured[key] = {int(a): float(b) for a, b in (t.split(":") for t in rest.split())}
+        for ln in entries:
+            if ln.startswith("ntt "):
+                key, choice = ln.rsplit(" ", 1)
+                assert key in measured, ln
+                times = measured[key]
+                assert int(choice) in times and times[int(choice)] == min(times.values()), ln
         c2 = q.Context(0)
         try:
             c2.tune_import(table)
-            assert c2.tune_export() == table
+            assert [ln for ln in c2.tune_export().splitlines()
+                    if ln and not ln.startswith("#")] == entries
             sid2 = c2.register_seed(dev(torch, sw), 2 ** 18)
             y2 = torch.full_like(y, -1)
             with c2.plan([(r[0], r[1], r[2], r[3], sid2) for r in rows], x, y2, graph=True) as p2:
