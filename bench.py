@@ -154,12 +154,39 @@ def roofline_for(kernel, work, unit, avg_s, traffic):
             "kernel": kernel}
 
 
-def source_digest():
+def _code_only(text):
+    """Source text without comments and with whitespace runs collapsed, so
+    that a comment edit does not count as a kernel change."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":           # string or character literal
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def source_digest(csrc=None):
+    """Digest of the library's sources (code only: comments and whitespace
+    excluded), which the committed counter figures are tied to."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2011_04130_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_2011_04130_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(f.encode() + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

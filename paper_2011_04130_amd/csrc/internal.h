@@ -16,7 +16,7 @@ enum KernelId {
   KID_ROWS_HASH,      // pass B: row transforms, seed product, inverse rows
   KID_ROWS_SEED,      // pass B for a seed window (forward only)
   KID_COLS_INV,       // pass C: inverse columns and bit packing
-  KID_FUSED_HASH,     // whole transform in one kernel (Nc <= 2^14)
+  KID_FUSED_HASH,     // whole transform in one kernel (Nc <= 2^15)
   KID_FUSED_SEED,
   KID_DIRECT,         // bit-packed direct product
   KID_DIRECT_PREP,    // output clear and raw-block reversal

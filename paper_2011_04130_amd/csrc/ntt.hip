@@ -24,7 +24,7 @@
 // pass B transforms each N2-long row, multiplies by the cached seed spectrum
 // and runs the inverse row transform without leaving registers/LDS; pass C
 // runs the inverse column transform and packs output bits with wave ballots.
-// For Nc <= 2^14 a single fused kernel does everything from raw bits to hash
+// For Nc <= 2^15 a single fused kernel does everything from raw bits to hash
 // bits.  Sub-transforms are radix-16 (radix-2/4/8 first round) register
 // butterflies with LDS exchanges between rounds.  The forward transform uses
 // decimation in frequency (natural order in, bit-reversed out) and the
