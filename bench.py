@@ -554,8 +554,11 @@ def bench_estimator(ctx, q, torch, qi, reps=10):
         ctx.profile(False)
         c, ms = pr["histogram"]
         us = ms / c * 1e3
+        # one byte per sample read: the HBM roofline of the histogram
         res["rates"][name] = {"us": round(us, 1), "samples_per_s": round(S / us * 1e6 / 1e9, 2),
                               "unit": "G samples/s", "kept": int(me["samples"]),
+                              "hbm_GB/s": round(S / us * 1e6 / 1e9, 1),
+                              "frac_of_8TB/s": round(S / us * 1e6 / PEAK_HBM, 4),
                               "h_mod": round(me["h_mod"], 4)}
     att = {}
     for bits in (5, 8):
