@@ -264,9 +264,25 @@ constexpr bool merge01() {
 // x0 + x1, and (x0 - x1) w_N^q = x0 w + x1 (p - w), no multiplication.
 // st(g, e, v) stores element e of round-1 group g.  b: round-1 group index
 // within its half, b < Geo<LOG1, 1>::s.
+// The twiddles of these two rounds for group index b, loaded before the
+// input bits are staged (they do not depend on them): w[a] = w_N^(a s1 + b)
+// of round 0, t1 the round-1 group twiddles.
+template <int LOG1>
+struct Tw01 {
+  uint32_t w[16];
+  uint2 t1[16];
+};
+template <int LOG1>
+__device__ __forceinline__ void load_tw01(int b, const uint2* __restrict__ tws, Tw01<LOG1>& t) {
+  using G0 = Geo<LOG1, 0>;
+  using G1 = Geo<LOG1, 1>;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) t.w[a] = tws[G0::toff + 2 * (a * G1::s + b) + 1].x;
+  group_tw<16, G1::s, false>(tws + G1::toff, b, t.t1);
+}
+
 template <int LOG1, class ST>
-__device__ __forceinline__ void fwd_round01_bits(int b, const uint2* __restrict__ tws,
-                                                 bool upper_zero,
+__device__ __forceinline__ void fwd_round01_bits(int b, const Tw01<LOG1>& tw01, bool upper_zero,
                                                  const uint32_t* __restrict__ wbits, int c,
                                                  ST&& st) {
   using G0 = Geo<LOG1, 0>;
@@ -279,20 +295,19 @@ __device__ __forceinline__ void fwd_round01_bits(int b, const uint2* __restrict_
       const int q = a * G1::s + b;
       const uint32_t x0 = (wbits[q] >> c) & 1u;
       v[0][a] = x0;
-      v[1][a] = x0 ? tws[G0::toff + 2 * q + 1].x : 0u;
+      v[1][a] = x0 ? tw01.w[a] : 0u;
     }
   } else {
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
       const int q = a * G1::s + b;
-      const uint32_t w = tws[G0::toff + 2 * q + 1].x;  // w_N^q, N = 2^LOG1
+      const uint32_t w = tw01.w[a];  // w_N^q, N = 2^LOG1
       const uint32_t x0 = (wbits[q] >> c) & 1u, x1 = (wbits[q + G0::s] >> c) & 1u;
       v[0][a] = x0 + x1;
       v[1][a] = (x0 ? w : 0u) + (x1 ? P - w : 0u);
     }
   }
-  uint2 t[16];
-  group_tw<16, G1::s, false>(tws + G1::toff, b, t);
+  const uint2 (&t)[16] = tw01.t1;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     dft_reg<16, false, true>(v[h]);
@@ -305,11 +320,29 @@ __device__ __forceinline__ void fwd_round01_bits(int b, const uint2* __restrict_
     for (int a = 0; a < 16; ++a) st(h * G1::s + b, a, v[h][a]);
 }
 
+// Twiddles of the inverse rounds 1 and 0 for group index b (loaded ahead of
+// the barrier before them): t1 the round-1 group twiddles, w[a] the Shoup
+// pair of w_N^-(a s1 + b) for round 0.
+template <int LOG1>
+struct TwInv10 {
+  uint2 t1[16];
+  uint2 w[16];
+};
+template <int LOG1>
+__device__ __forceinline__ void load_tw10(int b, const uint2* __restrict__ tws,
+                                          TwInv10<LOG1>& t) {
+  using G0 = Geo<LOG1, 0>;
+  using G1 = Geo<LOG1, 1>;
+  group_tw<16, G1::s, false>(tws + G1::toff, b, t.t1);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) t.w[a] = tws[G0::toff + 2 * (a * G1::s + b) + 1];
+}
+
 // Inverse rounds 1 and 0 (the last two of a column): ld(g, e) reads element e
 // of round-1 group g; out(q, e, v) receives position q + e N/2 (e = 0, 1).
 // The upper outputs are formed only when need_hi.
 template <int LOG1, class LD, class OUT>
-__device__ __forceinline__ void inv_round10(int b, const uint2* __restrict__ tws, bool need_hi,
+__device__ __forceinline__ void inv_round10(int b, const TwInv10<LOG1>& tw10, bool need_hi,
                                             LD&& ld, OUT&& out) {
   using G0 = Geo<LOG1, 0>;
   using G1 = Geo<LOG1, 1>;
@@ -319,8 +352,7 @@ __device__ __forceinline__ void inv_round10(int b, const uint2* __restrict__ tws
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int a = 0; a < 16; ++a) v[h][a] = ld(h * G1::s + b, a);
-  uint2 t[16];
-  group_tw<16, G1::s, false>(tws + G1::toff, b, t);
+  const uint2 (&t)[16] = tw10.t1;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -330,7 +362,7 @@ __device__ __forceinline__ void inv_round10(int b, const uint2* __restrict__ tws
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
     const int q = a * G1::s + b;
-    const uint2 w = tws[G0::toff + 2 * q + 1];  // w_N^-q
+    const uint2 w = tw10.w[a];  // w_N^-q
     const uint32_t u = v[0][a], tt = mul_shoup(v[1][a], w.x, w.y);
     out(q, 0, red2(u + tt));
     if (need_hi) out(q, 1, sub2(u, tt));
@@ -408,6 +440,11 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
   const uint32_t gstep = (uint32_t)j2 << (LOG_MAX - a.log_nc);
   const int l2 = a.log2;
 
+  // with one merged group per thread, its twiddles are loaded while the
+  // input bits are staged
+  constexpr bool MERGE1 = MERGE && merge01<LOG1>() && NS == Geo<LOG1, 1>::s;
+  Tw01<LOG1> tw01;
+  if constexpr (MERGE1) load_tw01<LOG1>(slot, tw.fwd, tw01);
   for (int j1 = threadIdx.x; j1 < (1 << LOG1); j1 += COLS * NS)
     wbits[j1] = stage_word(bits, mp, (j1 << l2) + bx * COLS, Nc);
   __syncthreads();
@@ -464,9 +501,17 @@ __device__ __forceinline__ void cols_fwd_body(const ColFwdArgs& a, const TwTable
     if constexpr (k < K - 1) __syncthreads();
   };
   if constexpr (MERGE && merge01<LOG1>()) {
-    for (int b = slot; b < Geo<LOG1, 1>::s; b += NS)
-      fwd_round01_bits<LOG1>(b, tw.fwd, a.upper_zero != 0, wbits, c,
+    if constexpr (MERGE1) {
+      fwd_round01_bits<LOG1>(slot, tw01, a.upper_zero != 0, wbits, c,
                              st_lds_k(std::integral_constant<int, 1>{}));
+    } else {
+      for (int b = slot; b < Geo<LOG1, 1>::s; b += NS) {
+        Tw01<LOG1> t01;
+        load_tw01<LOG1>(b, tw.fwd, t01);
+        fwd_round01_bits<LOG1>(b, t01, a.upper_zero != 0, wbits, c,
+                               st_lds_k(std::integral_constant<int, 1>{}));
+      }
+    }
     __syncthreads();
     static_for<2, K>(round);
   } else {
@@ -606,11 +651,24 @@ __device__ __forceinline__ void cols_inv_body(const ColInvArgs& a, const TwTable
     if constexpr (k > 0) __syncthreads();
   };
   if constexpr (MERGE && merge01<LOG1>()) {
-    static_for_down<2, K>(round);
     // outputs at j1 >= N1/2 lie at bit t >= (N1/2) N2 of the chunk
     const bool need_hi = ((int64_t)Geo<LOG1, 0>::s << l2) < (int64_t)ylimit;
-    for (int b = slot; b < Geo<LOG1, 1>::s; b += NS)
-      inv_round10<LOG1>(b, tw.inv, need_hi, ld_lds_k(std::integral_constant<int, 1>{}), st_bits);
+    if constexpr (NS == Geo<LOG1, 1>::s && K == 3) {
+      // one merged group per thread: its twiddles are loaded between the
+      // first round's work and its barrier, so they arrive during the wait
+      round_all<LOG1, 2, NS, CGMAX, true>(slot, tw.inv, ld_in, st_lds_k(std::integral_constant<int, 2>{}));
+      TwInv10<LOG1> t10;
+      load_tw10<LOG1>(slot, tw.inv, t10);
+      __syncthreads();
+      inv_round10<LOG1>(slot, t10, need_hi, ld_lds_k(std::integral_constant<int, 1>{}), st_bits);
+    } else {
+      static_for_down<2, K>(round);
+      for (int b = slot; b < Geo<LOG1, 1>::s; b += NS) {
+        TwInv10<LOG1> t10;
+        load_tw10<LOG1>(b, tw.inv, t10);
+        inv_round10<LOG1>(b, t10, need_hi, ld_lds_k(std::integral_constant<int, 1>{}), st_bits);
+      }
+    }
   } else {
     static_for_down<0, K>(round);
   }
