@@ -64,7 +64,7 @@ def ntt_plan(n, m):
     if k <= 15:
         l1, l2 = 0, k
     else:
-        l2 = min(14, max(10, k - 9))
+        l2 = min(14, max(10, 11 if k in (17, 18) else k - 9))
         l1 = k - l2
     return {"log_nc": k, "log1": l1, "log2": l2, "nx": nx, "ny": ny, "nwin": nx + ny - 1}
 

@@ -1362,8 +1362,10 @@ bool ntt_make_plan(uint64_t n, uint64_t m, NttPlan* p) {
     p->log1 = 0;
     p->log2 = k;
   } else {
-    // columns of 2^6 .. 2^9 points; rows of 2^10 up to 2^19, longer above
-    int l2 = k - 9;
+    // columns of 2^6 .. 2^9 points, rows of 2^10 .. 2^14; 2^9-point columns
+    // where the rows allow, except at 2^17 and 2^18 points, where 2^11-point
+    // rows (columns of 2^6 and 2^7) are 3-4 % faster on batches of blocks
+    int l2 = (k == 17 || k == 18) ? 11 : k - 9;
     l2 = l2 < 10 ? 10 : (l2 > MAX_LOG_ROW ? MAX_LOG_ROW : l2);
     p->log2 = l2;
     p->log1 = k - l2;
