@@ -39,7 +39,7 @@ P_NTT = 998244353
 PEAK_INT32_MUL = 39.3e12
 PEAK_BITOP = 39.3e12
 PEAK_HBM = 8.0e12
-PEAK_INT8 = 5.0e15           # dense int8 MFMA
+PEAK_FP4 = 10.1e15           # dense fp4 MFMA (the matrix-core hash runs on fp4 operands)
 
 
 def progress(msg):
@@ -609,11 +609,11 @@ def bench_sweep(ctx, q, torch, qi, reps=3):
                 agree = agree and bool(torch.equal(first, y))
             row[name] = round(tot / t / 1e9, 2)
             if name == "mfma":
-                # the dense int8 product: 2 m n operations per block
+                # the dense fp4 product: 2 m n operations per block
                 pops = 2.0 * m * n * B / t / 1e15
                 row["mfma_roofline"] = {"bound": "mfma", "achieved": round(pops, 3),
-                                        "peak": PEAK_INT8 / 1e15, "unit": "POP/s int8",
-                                        "frac": round(pops * 1e15 / PEAK_INT8, 4)}
+                                        "peak": PEAK_FP4 / 1e15, "unit": "PFLOP/s fp4",
+                                        "frac": round(pops * 1e15 / PEAK_FP4, 4)}
         ctx.unregister_seed(sid)
         row["paths_agree"] = agree
         res["2^%d" % lg] = row
@@ -705,7 +705,7 @@ def bench_serve(ctx, q, torch, qi, seconds=0.6, nwin=64, min_requests=10000):
             ms_ = st_["m_block"] or ns_ * 5 // 8  # the windows' m_s (H = 5 bits per sample)
             res["rates"][str(rate)] = {
                 "m_block": ms_,
-                "served_int8_ops_frac": round(2.0 * ms_ * ns_ * nb / PEAK_INT8 / span, 4),
+                "served_mfma_ops_frac": round(2.0 * ms_ * ns_ * nb / PEAK_FP4 / span, 4),
                 "requests": N, "p50_ms": round(float(lat[N // 2]) * 1e3, 3),
                 "p99_ms": round(float(lat[min(N - 1, int(N * 0.99))]) * 1e3, 3),
                 "served_gbps": round(float(size.sum()) / span / 1e9, 3),
@@ -769,7 +769,7 @@ def bench_counters(ctx, q, torch, qi):
                                             ("ntt_cols_fwd", "ntt_rows_hash",
                                              "ntt_cols_inv")}},
             "direct_n2^23": {"n": n, "m": m, "gf2_macs": n * m, "bitops_32": n * m // 32},
-            "mfma_n2^12": {"n": n2, "m": m2, "blocks": B, "int8_ops": 2 * n2 * m2 * B}}
+            "mfma_n2^12": {"n": n2, "m": m2, "blocks": B, "fp4_ops": 2 * n2 * m2 * B}}
 
 
 def main():

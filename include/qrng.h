@@ -52,7 +52,7 @@ typedef enum {
   QRNG_PATH_AUTO = 0,   /* library picks (autotuned plan table if loaded) */
   QRNG_PATH_DIRECT = 1, /* bit-packed AND/parity mat-vec, O(mn); n+m-1 < 2^34 */
   QRNG_PATH_NTT = 2,    /* exact convolution mod 998244353, O(L log L) */
-  QRNG_PATH_MFMA = 3    /* int8 matrix-core product, shared-seed batches */
+  QRNG_PATH_MFMA = 3    /* matrix-core product (fp4 operands, exact fp32 sums), shared-seed batches */
 } qrng_path;
 
 /* The set U over which the statistical distance is taken (Sec. II.C). */

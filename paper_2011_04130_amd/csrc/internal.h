@@ -21,7 +21,7 @@ enum KernelId {
   KID_DIRECT,         // bit-packed direct product
   KID_DIRECT_PREP,    // output clear and raw-block reversal
   KID_HIST,           // sample histogram
-  KID_MFMA,           // int8 matrix-core product
+  KID_MFMA,           // matrix-core product (fp4 operands)
   KID_MOD_TAIL,       // identity block of the modified Toeplitz hash
   KID_FFT64,          // the paper's float64 method (all its launches)
   KID_COUNT
@@ -222,7 +222,7 @@ hipError_t fft64_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_b
                       uint64_t* y, unsigned long long* err, uint32_t* work, hipStream_t s);
 
 // -------------------------------------------------------------- MFMA path
-// `batch` blocks sharing one seed as one int8 matrix product (strides as in
+// `batch` blocks sharing one seed as one matrix-core product (strides as in
 // ntt_hash).  No workspace.
 hipError_t mfma_hash(const uint32_t* x_bits, uint64_t n, const uint32_t* seed_bits, uint64_t m,
                      uint32_t* y_bits, int batch, uint64_t x_stride_bits,

@@ -1,4 +1,4 @@
-"""GPU parity of the multi-block paths: the int8 matrix-core product over
+"""GPU parity of the multi-block paths: the matrix-core product (fp4 operands) over
 blocks sharing one seed, and batches of blocks against the oracle and
 against the single-block call (0 differing bits)."""
 import numpy as np
