@@ -141,3 +141,31 @@ def test_sweep_full_size_every_block(torch, ctx, sweep_stream, lg):
                 assert np.array_equal(oracle.unpack_bits(yb, m)[rows], want), "block %d" % b
     finally:
         ctx.unregister_seed(sid)
+
+
+@pytest.mark.parametrize("n,nblk", [(1 << 15, 200), (3 << 14, 130), ((3 << 14) + 64, 64)])
+def test_default_path_near_matrix_core_limit(torch, ctx, n, nblk):
+    """Shared-seed batches around the default path's matrix-core limit (n <=
+    3 2^14 with >= 32 blocks): the default path's bits equal the transform's
+    and the direct product's for every block, and the first and last blocks
+    equal the oracle's; just above the limit the default is the transform."""
+    m = n * 5 // 8
+    log("near limit n=%d blocks=%d" % (n, nblk))
+    sw = qi.gen_seed_words(n + m - 1, n + 5)
+    sid = ctx.register_seed(dev(torch, sw), n + m - 1)
+    xw = qi.gen_bits(nblk * n, n + 7)
+    xt = dev(torch, xw)
+    yw = (m + 63) // 64
+    try:
+        outs = {}
+        for path in (0, 1, 2, 3):
+            yt = torch.full((nblk * yw,), -1, dtype=torch.int64, device="cuda:0")
+            ctx.hash_strided(xt, n, n // 64, sid, m, yt, yw, nblk, path=path)
+            outs[path] = host(yt)
+        for path in (1, 2, 3):
+            assert np.array_equal(outs[0], outs[path]), "path %d differs from the default" % path
+        for b in (0, nblk - 1):
+            want = oracle.toeplitz_packed(xw[b * (n // 64):(b + 1) * (n // 64)], n, sw, m)
+            assert np.array_equal(outs[0][b * yw:(b + 1) * yw], want), "block %d" % b
+    finally:
+        ctx.unregister_seed(sid)
