@@ -15,14 +15,15 @@
 // issue time of the int8 instruction's 32.
 //
 // Tiling: a workgroup owns 256 output rows x 128 blocks; each wave owns 32
-// blocks and all eight 32-row tiles (eight 32x32 accumulators), so the
-// wave's raw-bit fragment, which takes VALU work to expand to fp4, feeds
-// eight instructions.  A fragments (the Toeplitz matrix) come from an LDS
-// copy of the reversed seed window already expanded to fp4, shared by the
-// four waves.  Fragment layout: lane l holds row or column l % 32 and 32
-// k-values of lane group l / 32 (dword q, nibble i: k = 32 (l / 32) + 8 q +
-// i), the same k order on A and B, so the contraction over k is exact
-// whatever order the hardware adds in.
+// blocks and all eight 32-row tiles (eight 32x32 accumulators).  Fragment
+// layout: lane l holds row or column l % 32 and 32 k-values of lane group
+// l / 32, dword q nibble i holding k = 32 (l / 32) + 4 i + q on both A and B
+// (any order common to both gives the same sums).  So B's dword q is the
+// raw word's bits q, q+4, ..., q+28 moved to the nibbles' 1.0 bit, one
+// shift and one mask; and an A fragment depends only on where its window
+// starts, so each K-chunk builds in LDS a table with one 16-byte row per
+// window start (the four dwords of the fragment starting there, shared by
+// the four waves) and every A fragment is one 16-byte LDS read.
 #include "common.h"
 #include "internal.h"
 
@@ -49,23 +50,15 @@ constexpr int KC = 512;            // raw bits per K-chunk
 constexpr int KW = KC / 32;        // raw words per block per K-chunk
 constexpr int KS = KC / 64;        // instructions per tile per K-chunk
 constexpr int XROW = KW + 1;       // padded LDS row (words) of one block's chunk
-constexpr int RSPAN = MT + KC;     // nibbles of one shifted copy of the seed window
-constexpr int RWORDS = RSPAN / 8 + 5;  // dwords of the window copy (+ read slack)
+constexpr int NV = MT + KC;        // window starts of one K-chunk (fragment table rows)
+constexpr int VPT = NV / 256;      // table rows each thread builds
+constexpr uint32_t FP4_ONES = 0x22222222u;  // fp4 1.0 (0b0010) in every nibble
 constexpr uint32_t SCALE_ONE = 0x7F;   // E8M0 exponent of 1.0
-
-// 8 bits -> 8 nibbles: bit i to bit 4i + 1 (fp4 1.0 = 0b0010, 0 = 0b0000)
-__device__ __forceinline__ uint32_t spread8(uint32_t b) {
-  uint32_t x = (b & 0xFFu) << 1;
-  x = (x | (x << 12)) & 0x001E001Eu;
-  x = (x | (x << 6)) & 0x06060606u;
-  x = (x | (x << 3)) & 0x22222222u;
-  return x;
-}
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mfma(MfmaArgs a) {
   typedef float v16f __attribute__((ext_vector_type(16)));
   typedef int v8i __attribute__((ext_vector_type(8)));
-  __shared__ uint32_t rs[2][RWORDS];
+  __shared__ uint4 fv[2][NV];
   __shared__ uint32_t xs[2][NTB * XROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * MT;
@@ -88,7 +81,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // blocks bg + tid/4 + 64 e, words 4 (tid % 4) .. + 3
   constexpr int XPT = NTB * KW / (4 * 256);
   static_assert(NTB * KW % (4 * 256) == 0 && KW % 4 == 0, "raw words per thread");
-  static_assert(RWORDS <= 256, "one window dword per thread");
+  static_assert(VPT * 256 == NV, "fragment table rows per thread");
   const int64_t nw32 = 2 * (((int64_t)a.n + 63) >> 6);
   const uint32_t b0 = bg + (uint32_t)(tid >> 2);
   const int q0 = 4 * (tid & 3);
@@ -96,7 +89,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const uint32_t* xrow = a.x + ((uint64_t)b0 * a.x_zs >> 5) + q0;
   const bool full_group = bg + NTB <= a.nblocks;
   uint4 pre_x[XPT];
-  uint32_t pre_s0 = 0, pre_s1 = 0;
+  uint32_t pre_s[3] = {0u, 0u, 0u};
   auto seed_word = [&](int64_t w) -> uint32_t {
     uint32_t v = (w >= 0 && w < nsw) ? a.seed[w] : 0u;
     const int64_t top = L - 32 * w;
@@ -105,12 +98,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   };
   auto fetch = [&](int64_t k0) {
     const int64_t base = n - 1 + i0 - k0 + (MT - 1);
-    if (tid < RWORDS) {
-      // window dword tid: seed bits base-8 tid-7 .. base-8 tid
-      const int64_t p = base - 8 * tid - 7;
-      const int64_t w = p >> 5;
-      pre_s0 = seed_word(w);
-      pre_s1 = ((p & 31) > 24) ? seed_word(w + 1) : 0u;
+    {
+      // table rows v = VPT tid + e read the 32 seed bits from base - v - 31:
+      // together the bits from base - VPT tid - 31 - (VPT - 1), three words
+      const int64_t wb = (base - VPT * tid - 31 - (VPT - 1)) >> 5;
+      pre_s[0] = seed_word(wb);
+      pre_s[1] = seed_word(wb + 1);
+      pre_s[2] = seed_word(wb + 2);
     }
     const int64_t kw = k0 >> 5;
     if (full_group && k0 + KC <= n) {
@@ -158,13 +152,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       dst[2] = pre_x[e].z;
       dst[3] = pre_x[e].w;
     }
-    if (tid < RWORDS) {
-      // nibbles 8j .. 8j+7 = seed bits base-8j down to base-8j-7 (j = tid)
-      const int64_t base = n - 1 + i0 - k0 + (MT - 1);
-      const uint32_t ps = (uint32_t)((base - 8 * tid - 7) & 31);
-      uint32_t w8 = pre_s0 >> ps;
-      if (ps > 24) w8 |= pre_s1 << (32 - ps);
-      rs[c][tid] = spread8(__builtin_bitreverse32(w8 & 0xFFu) >> 24);
+    {
+      // row v: dword q, nibble i = value u = v + 4i + q, i.e. seed bit
+      // base - v - q - 4i = bit 31 - q - 4i of the 32 bits w from base - v -
+      // 31; after the bit reversal R, that is bit 4i + q, moved to the
+      // nibble's 1.0 bit (4i + 1) by one shift and one mask
+      const int64_t p0 = n - 1 + i0 - k0 + (MT - 1) - VPT * tid - 31;
+      const uint32_t o0 = (uint32_t)((p0 - (VPT - 1)) & 31);
+#pragma unroll
+      for (int e = 0; e < VPT; ++e) {
+        const uint32_t o = o0 + (VPT - 1) - e;  // bit offset in the three words, < 34
+        const uint32_t w = o < 32 ? __builtin_amdgcn_alignbit(pre_s[1], pre_s[0], o)
+                                  : __builtin_amdgcn_alignbit(pre_s[2], pre_s[1], o - 32);
+        const uint32_t R = __builtin_bitreverse32(w);
+        fv[c][VPT * tid + e] = make_uint4((R << 1) & FP4_ONES, R & FP4_ONES,
+                                          (R >> 1) & FP4_ONES, (R >> 2) & FP4_ONES);
+      }
     }
   };
   fetch(0);
@@ -174,24 +177,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   for (int64_t k0 = 0; k0 < n; k0 += KC, c ^= 1) {
     const bool more = k0 + KC < n;
     if (more) fetch(k0 + KC);
-    const uint32_t* rsc = rs[c];
+    const uint4* fvc = fv[c];
     const uint32_t* xsc = xs[c];
-    // A fragment of row tile t at step ks: rows 32t + rl, k = 64 ks + 32 g +
-    // j, u0 = MT-1 - (32t + rl) + 64 ks + 32 g = ub - 32 t + 64 ks.  Tiles
-    // (t, ks) and (t+2, ks+1) share u0, so after a chunk's first step only
-    // tiles 0, 1 are new.  The nibble shift ub % 8 is the same for every
-    // (t, ks), and the dword index moves by constants (LDS immediate offsets).
-    const int ub = (MT - 1) - rl + 32 * g;
-    const uint32_t sh = (uint32_t)(ub & 7) * 4u;
-    const uint32_t* rpb = rsc + (ub >> 3);
+    // A fragment of row tile t at step ks: rows 32t + rl, dword q nibble i =
+    // k 64 ks + 32 g + 4i + q, i.e. value u0 + 4i + q with u0 = MT-1 - (32t +
+    // rl) + 64 ks + 32 g = ub - 32 t + 64 ks: table row u0, one 16-byte
+    // read at a per-lane address plus a constant.  Tiles (t, ks) and (t+2,
+    // ks+1) share u0, so after a chunk's first step only tiles 0, 1 are new.
+    const uint4* fvb = fvc + ((MT - 1) - rl + 32 * g);
     auto a_frag = [&](int t, int ks) {
-      const uint32_t* rp = rpb + (8 * ks - 4 * t);
-      const uint32_t d0 = rp[0], d1 = rp[1], d2 = rp[2], d3 = rp[3], d4 = rp[4];
+      const uint4 d = fvb[64 * ks - 32 * t];
       v4i f;
-      f.x = (int)__builtin_amdgcn_alignbit(d1, d0, sh);
-      f.y = (int)__builtin_amdgcn_alignbit(d2, d1, sh);
-      f.z = (int)__builtin_amdgcn_alignbit(d3, d2, sh);
-      f.w = (int)__builtin_amdgcn_alignbit(d4, d3, sh);
+      f.x = (int)d.x;
+      f.y = (int)d.y;
+      f.z = (int)d.z;
+      f.w = (int)d.w;
       return f;
     };
     v4i af[8];
@@ -210,10 +210,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       // fp4 operands take the low four dwords of the eight-dword argument
       const v4i z4 = {0, 0, 0, 0};
       v4i b4;
-      b4.x = (int)spread8(xw);
-      b4.y = (int)spread8(xw >> 8);
-      b4.z = (int)spread8(xw >> 16);
-      b4.w = (int)spread8(xw >> 24);
+      b4.x = (int)((xw << 1) & FP4_ONES);
+      b4.y = (int)(xw & FP4_ONES);
+      b4.z = (int)((xw >> 1) & FP4_ONES);
+      b4.w = (int)((xw >> 2) & FP4_ONES);
       const v8i bf = __builtin_shufflevector(b4, z4, 0, 1, 2, 3, 4, 5, 6, 7);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {

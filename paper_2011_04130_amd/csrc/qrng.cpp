@@ -239,9 +239,9 @@ qrng_status check_hash_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const 
 // transform about 40 (n+m) log2(n+m) modular ops; the single-block crossover
 // on MI355X sits near n = 2^15.  Many blocks sharing a seed make the fp4
 // matrix-core product the fastest up to n = 3 2^14 (measured on 2^30-bit
-// batches at m = 5n/8: 849 vs 275 Gbit/s direct at n = 2^12, 285 vs 95
-// Gbit/s NTT at n = 2^14, 148 Gbit/s at 2^15, about 74 at 2^16 against the
-// NTT's 83).
+// batches at m = 5n/8: 905 vs 278 Gbit/s direct at n = 2^12, 319 vs 95
+// Gbit/s NTT at n = 2^14, 170 Gbit/s at 2^15, about 85 at 2^16 against the
+// NTT's 84).
 int choose_path(uint64_t n, uint64_t m, uint64_t batch = 1) {
   if (batch >= 32 && n <= 3u * (1u << 14)) return QRNG_PATH_MFMA;
   if (n < (1u << 15)) return QRNG_PATH_DIRECT;
