@@ -238,12 +238,13 @@ qrng_status check_hash_args(qrng_ctx* ctx, const uint64_t* x, uint64_t n, const 
 // Default path choice: the direct product costs m n / 32 bit-ops, the
 // transform about 40 (n+m) log2(n+m) modular ops; the single-block crossover
 // on MI355X sits near n = 2^15.  Many blocks sharing a seed make the fp4
-// matrix-core product the fastest up to n = 3 2^14 (measured on 2^30-bit
-// batches at m = 5n/8: 905 vs 278 Gbit/s direct at n = 2^12, 319 vs 95
-// Gbit/s NTT at n = 2^14, 170 Gbit/s at 2^15, about 85 at 2^16 against the
-// NTT's 84).
+// matrix-core product (cost m n per block) the fastest while m n stays within
+// that of n = 2^16 at m = 5n/8 (measured on 2^30-bit batches at m = 5n/8,
+// matrix cores against the transform: 905 vs 105 Gbit/s at n = 2^12, 319 vs
+// 95 at 2^14, 170 vs 83 at 2^15, 114 vs 62 at 3 2^14, 86.6 vs 82.5 at 2^16,
+// 43.7 vs 81 at 2^17).
 int choose_path(uint64_t n, uint64_t m, uint64_t batch = 1) {
-  if (batch >= 32 && n <= 3u * (1u << 14)) return QRNG_PATH_MFMA;
+  if (batch >= 32 && n * m <= (5ull << 29)) return QRNG_PATH_MFMA;
   if (n < (1u << 15)) return QRNG_PATH_DIRECT;
   NttPlan p;
   if (!ntt_make_plan(n, m, &p)) return QRNG_PATH_DIRECT;

@@ -143,12 +143,14 @@ def test_sweep_full_size_every_block(torch, ctx, sweep_stream, lg):
         ctx.unregister_seed(sid)
 
 
-@pytest.mark.parametrize("n,nblk", [(1 << 15, 200), (3 << 14, 130), ((3 << 14) + 64, 64)])
+@pytest.mark.parametrize("n,nblk", [(1 << 15, 200), (3 << 14, 130), (1 << 16, 64),
+                                    ((1 << 16) + 512, 40)])
 def test_default_path_near_matrix_core_limit(torch, ctx, n, nblk):
-    """Shared-seed batches around the default path's matrix-core limit (n <=
-    3 2^14 with >= 32 blocks): the default path's bits equal the transform's
-    and the direct product's for every block, and the first and last blocks
-    equal the oracle's; just above the limit the default is the transform."""
+    """Shared-seed batches around the default path's matrix-core limit (m n <=
+    5 2^29 with >= 32 blocks, n = 2^16 at m = 5n/8): the default path's bits
+    equal the transform's, the matrix cores' and the direct product's for
+    every block, and the first and last blocks equal the oracle's; just above
+    the limit the default is the transform."""
     m = n * 5 // 8
     log("near limit n=%d blocks=%d" % (n, nblk))
     sw = qi.gen_seed_words(n + m - 1, n + 5)
