@@ -144,7 +144,7 @@ SIZES = [(1, 1), (2, 1), (5, 3), (31, 17), (64, 64), (65, 1), (100, 100), (1000,
 
 
 @pytest.mark.parametrize("n,m", SIZES)
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_hash_matches_oracle(torch, ctx, n, m, path):
     log("hash n=%d m=%d path=%d" % (n, m, path))
     rng = np.random.default_rng(n * 7919 + m)
@@ -265,7 +265,7 @@ def test_seeded_and_batched_equal_single(torch, ctx):
 # ------------------------------------------------ one asynchronous pass
 
 @pytest.mark.parametrize("cfg_k,path,cap_frac", [(0, 1, 1.0), (0, 2, 1.0), (0, 2, 0.5),
-                                                  (1, 2, 1.0), (1, 1, 0.75)])
+                                                  (0, 3, 0.75), (1, 2, 1.0), (1, 1, 0.75)])
 def test_extract_matches_oracle(torch, ctx, cfg_k, path, cap_frac):
     """Device min-entropy, device m and the hash in one call equal the oracle."""
     c = qi.config(cfg_k)
