@@ -248,7 +248,7 @@ def test_seeded_and_batched_equal_single(torch, ctx):
         xw = qi.gen_bits(64 * x_off, 78)
         xt = dev(torch, xw)
         y_pool = torch.zeros(y_off + 4, dtype=torch.int64, device="cuda:0")
-        for path in (0, 1, 2):
+        for path in (0, 1, 2, 3):
             y_pool.zero_()
             ctx.hash_batched_host(blocks, xt, y_pool, path=path)
             yp = host(y_pool)
@@ -340,7 +340,11 @@ def test_extract_estimate_in_column_pass(torch, ctx, S):
         ctx.unregister_seed(sid)
 
 
-def test_extract_security_term_and_given_model(torch, ctx):
+@pytest.mark.parametrize("path", [2, 3])
+def test_extract_security_term_and_given_model(torch, ctx, path):
+    """The device m with a security term (m not a multiple of 32) and the
+    given-model readings, on the transform and on the matrix cores (whose
+    row tiles then end inside a 32-row word)."""
     c = qi.config(0)
     s = qi.gen_adc(c["S"], 12.0, seed=31)
     n = 8 * c["S"]
@@ -355,7 +359,7 @@ def test_extract_security_term_and_given_model(torch, ctx):
             m = oracle.output_bits(n, 8, ref["h_mod"], eps)
             m_out = torch.zeros(1, dtype=torch.int64, device="cuda:0")
             y = ctx.extract(torch.from_numpy(s).to("cuda:0"), sid, n, m_out=m_out, model=model,
-                            mu=mu, sigma=sigma, u_mode=u_mode, log2_inv_eps=eps, path=2)
+                            mu=mu, sigma=sigma, u_mode=u_mode, log2_inv_eps=eps, path=path)
             torch.cuda.synchronize()
             assert int(m_out.item()) == m
             want = oracle.toeplitz_packed(qi.samples_as_words(s), n, sw, m)
