@@ -46,7 +46,7 @@ struct MfmaArgs {
 
 constexpr int MT = 256;            // rows per workgroup (8 tiles of 32)
 constexpr int NTB = 128;           // blocks per workgroup (4 waves x 32)
-constexpr int KC = 512;            // raw bits per K-chunk
+constexpr int KC = 1024;           // raw bits per K-chunk
 constexpr int KW = KC / 32;        // raw words per block per K-chunk
 constexpr int KS = KC / 64;        // instructions per tile per K-chunk
 constexpr int XROW = KW + 1;       // padded LDS row (words) of one block's chunk
@@ -77,15 +77,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int g = lane >> 5;
   const int rl = lane & 31;
 
-  // raw words of one K-chunk, one chunk ahead in registers: thread's rows are
-  // blocks bg + tid/4 + 64 e, words 4 (tid % 4) .. + 3
-  constexpr int XPT = NTB * KW / (4 * 256);
-  static_assert(NTB * KW % (4 * 256) == 0 && KW % 4 == 0, "raw words per thread");
+  // raw words of one K-chunk, one chunk ahead in registers: TPB threads
+  // share a block's KW words (16 bytes each); thread's rows are blocks
+  // bg + tid/TPB + BPE e, words 4 (tid % TPB) .. + 3
+  constexpr int TPB = KW / 4, BPE = 256 / TPB;
+  constexpr int XPT = NTB / BPE;
+  static_assert(KW % 4 == 0 && 256 % TPB == 0 && NTB % BPE == 0, "raw words per thread");
   static_assert(VPT * 256 == NV, "fragment table rows per thread");
   const int64_t nw32 = 2 * (((int64_t)a.n + 63) >> 6);
-  const uint32_t b0 = bg + (uint32_t)(tid >> 2);
-  const int q0 = 4 * (tid & 3);
-  const uint64_t bstride = (uint64_t)64 * a.x_zs >> 5;
+  const uint32_t b0 = bg + (uint32_t)(tid / TPB);
+  const int q0 = 4 * (tid % TPB);
+  const uint64_t bstride = (uint64_t)BPE * a.x_zs >> 5;
   const uint32_t* xrow = a.x + ((uint64_t)b0 * a.x_zs >> 5) + q0;
   const bool full_group = bg + NTB <= a.nblocks;
   uint4 pre_x[XPT];
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
-      const uint32_t b = b0 + 64 * e;
+      const uint32_t b = b0 + BPE * e;
       const int64_t w0 = kw + q0;
       uint32_t v[4] = {0u, 0u, 0u, 0u};
       if (b < a.nblocks) {
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   auto stage = [&](int c, int64_t k0) {
 #pragma unroll
     for (int e = 0; e < XPT; ++e) {
-      uint32_t* dst = xs[c] + ((tid >> 2) + 64 * e) * XROW + q0;
+      uint32_t* dst = xs[c] + (tid / TPB + BPE * e) * XROW + q0;
       dst[0] = pre_x[e].x;
       dst[1] = pre_x[e].y;
       dst[2] = pre_x[e].z;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const uint32_t o0 = (uint32_t)((p0 - (VPT - 1)) & 31);
 #pragma unroll
       for (int e = 0; e < VPT; ++e) {
-        const uint32_t o = o0 + (VPT - 1) - e;  // bit offset in the three words, < 34
+        const uint32_t o = o0 + (VPT - 1) - e;  // bit offset in the three words, < 32 + VPT
         const uint32_t w = o < 32 ? __builtin_amdgcn_alignbit(pre_s[1], pre_s[0], o)
                                   : __builtin_amdgcn_alignbit(pre_s[2], pre_s[1], o - 32);
         const uint32_t R = __builtin_bitreverse32(w);
@@ -198,8 +200,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int t = 0; t < 8; ++t) af[t] = a_frag(t, 0);
     const int bl = wave * 32 + rl;
+    // the chunk's steps in runs of eight (the register names of the fragment
+    // rotation repeat every four steps, so a run ends where it began)
+#pragma unroll 1
+    for (int kh = 0; kh < KS; kh += 8)
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int kq = 0; kq < 8; ++kq) {
+      const int ks = kh + kq;
       if (ks > 0) {
 #pragma unroll
         for (int t = 7; t >= 2; --t) af[t] = af[t - 2];
